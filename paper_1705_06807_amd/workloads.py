@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs: reaction networks, problems and batches.
+
+This module only builds input data (stoichiometry, rate constants, regions,
+thresholds, seeds).  It holds none of the method's arithmetic, so the CPU
+oracle's tests and the HIP path's tests can both draw their inputs from it.
+
+Networks are described in one factored form used throughout the project:
+
+    lambda_j(x, c) = k_j * phi_j1(x) * phi_j2(x) * ...      (left to right)
+    k_j = c[rate_param_j] * kappa_j     (k_j = kappa_j when rate_param_j < 0)
+
+with two factor kinds:
+
+* ``FALLING``  phi(x) = x_s (x_s - 1) ... (x_s - order + 1)   (mass action)
+* ``HILL_REP`` phi(x) = 1 / (1 + (x_s / K) ** c[hill_param])   (repression)
+
+Stoichiometry rows are net changes (products minus reactants), which is what
+both model tables of the paper list (Sec. IV, Tables I and IV).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+FALLING = 0
+HILL_REP = 1
+
+STEPS = 0
+TIME = 1
+
+MAX_SPECIES = 4
+MAX_REACTIONS = 8
+MAX_FACTORS = 2
+MAX_PARAMS = 8
+
+
+@dataclasses.dataclass(frozen=True)
+class Factor:
+    kind: int
+    species: int
+    order: int = 0          # FALLING only
+    K: float = 1.0          # HILL_REP only: x_s is divided by K
+    hill_param: int = -1    # HILL_REP only: index of the exponent in c
+
+
+@dataclasses.dataclass(frozen=True)
+class Reaction:
+    rate_param: int
+    kappa: float
+    factors: Sequence[Factor]
+    stoich: Sequence[int]
+
+
+@dataclasses.dataclass(frozen=True)
+class Network:
+    name: str
+    n_species: int
+    n_params: int
+    reactions: Sequence[Reaction]
+    param_names: Sequence[str] = ()
+
+    @property
+    def n_reactions(self) -> int:
+        return len(self.reactions)
+
+    def stoich_matrix(self) -> np.ndarray:
+        return np.array([list(r.stoich) for r in self.reactions], dtype=np.int32)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One ParRep solve: the paper's problem data (Sec. II A, Alg. 1) plus outputs."""
+    net: Network
+    c: Sequence[float]
+    x0: Sequence[int]
+    region_w: Sequence[int]
+    region_theta: int
+    R: int
+    decorr_mode: int = TIME
+    decorr: float = 1.0
+    dephase_mode: int = TIME
+    dephase: float = 1.0
+    T: float = 200.0
+    t_burn: float = 0.0
+    hist_lo: Sequence[int] = (0,)
+    hist_hi: Sequence[int] = (1000,)
+    rer_eps: Optional[Sequence[float]] = None
+    seed: int = 0
+    instance_id: int = 0
+    max_events: int = 0
+
+    def nbins(self) -> int:
+        n = 1
+        for lo, hi in zip(self.hist_lo, self.hist_hi):
+            n *= hi - lo + 1
+        return n
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+# --------------------------------------------------------------------------
+# Networks
+# --------------------------------------------------------------------------
+
+def schlogl_classic(A: float = 1e5, B: float = 2e5) -> Network:
+    """Schloegl model with binomial mass action and baths A, B folded into kappa.
+
+    A+2X->3X: c1/2*A*x(x-1); 3X->A+2X: c2/6*x(x-1)(x-2); B->X: c3*B; X->B: c4*x.
+    """
+    return Network(
+        name="schlogl_classic",
+        n_species=1,
+        n_params=4,
+        param_names=("c1", "c2", "c3", "c4"),
+        reactions=(
+            Reaction(0, A / 2.0, (Factor(FALLING, 0, order=2),), (1,)),
+            Reaction(1, 1.0 / 6.0, (Factor(FALLING, 0, order=3),), (-1,)),
+            Reaction(2, B, (), (1,)),
+            Reaction(3, 1.0, (Factor(FALLING, 0, order=1),), (-1,)),
+        ),
+    )
+
+
+SCHLOGL_CLASSIC_C = (3e-7, 1e-4, 1e-3, 3.5)
+
+
+def schlogl_paper(V: float = 25.0, a: float = 1.0, b: float = 2.0) -> Network:
+    """Schloegl model in the paper's form (Sec. IV A, Table I) at system size V."""
+    return Network(
+        name="schlogl_paper",
+        n_species=1,
+        n_params=4,
+        param_names=("c1", "c2", "c3", "c4"),
+        reactions=(
+            Reaction(0, a / V, (Factor(FALLING, 0, order=2),), (1,)),
+            Reaction(1, 1.0 / (V * V), (Factor(FALLING, 0, order=3),), (-1,)),
+            Reaction(2, b * V, (), (1,)),
+            Reaction(3, 1.0, (Factor(FALLING, 0, order=1),), (-1,)),
+        ),
+    )
+
+
+SCHLOGL_PAPER_C = (3.0, 0.6, 0.25, 2.95)
+
+
+def toggle(omega: float) -> Network:
+    """Two-gene toggle switch, parameters ordered (a1, a2, beta, gamma).
+
+    0->U: Omega*a1/(1+(v/Omega)^beta); U->0: u; 0->V: Omega*a2/(1+(u/Omega)^gamma); V->0: v.
+    """
+    om = float(omega)
+    return Network(
+        name="toggle",
+        n_species=2,
+        n_params=4,
+        param_names=("a1", "a2", "beta", "gamma"),
+        reactions=(
+            Reaction(0, om, (Factor(HILL_REP, 1, K=om, hill_param=2),), (1, 0)),
+            Reaction(-1, 1.0, (Factor(FALLING, 0, order=1),), (-1, 0)),
+            Reaction(1, om, (Factor(HILL_REP, 0, K=om, hill_param=3),), (0, 1)),
+            Reaction(-1, 1.0, (Factor(FALLING, 1, order=1),), (0, -1)),
+        ),
+    )
+
+
+TOGGLE_C = (3.0, 3.0, 2.0, 2.0)
+
+
+def pure_death(rate: float = 1.0) -> Network:
+    """X -> 0 at rate c1*x: reaches the absorbing state x = 0 (a0 = 0)."""
+    return Network(
+        name="pure_death",
+        n_species=1,
+        n_params=1,
+        param_names=("c1",),
+        reactions=(Reaction(0, 1.0, (Factor(FALLING, 0, order=1),), (-1,)),),
+    )
+
+
+def birth_death(kb: float = 1.0) -> Network:
+    """0 -> X at c1, X -> 0 at c2*x (Poisson stationary law)."""
+    return Network(
+        name="birth_death",
+        n_species=1,
+        n_params=2,
+        param_names=("c1", "c2"),
+        reactions=(
+            Reaction(0, 1.0, (), (1,)),
+            Reaction(1, 1.0, (Factor(FALLING, 0, order=1),), (-1,)),
+        ),
+    )
+
+
+# --------------------------------------------------------------------------
+# Problems at the benchmark configurations
+# --------------------------------------------------------------------------
+
+def c1_schlogl(seed: int = 0, instance_id: int = 0, R: int = 32, T: float = 200.0) -> Problem:
+    """Classic Schloegl, x0 = 85, regions x < 250 / x >= 250, R = 32, t_c = t_p = 1.0."""
+    return Problem(
+        net=schlogl_classic(), c=SCHLOGL_CLASSIC_C, x0=(85,), region_w=(1,), region_theta=250,
+        R=R, decorr_mode=TIME, decorr=1.0, dephase_mode=TIME, dephase=1.0,
+        T=T, t_burn=T / 2.0, hist_lo=(0,), hist_hi=(1000,), rer_eps=(0.01,) * 4,
+        seed=seed, instance_id=instance_id)
+
+
+def c2_toggle(seed: int = 0, instance_id: int = 0, omega: float = 50.0, R: int = 1024,
+              T: float = 2e4) -> Problem:
+    """Toggle switch, x0 = (0,0), regions u > v / u <= v, histogram [0, 8*Omega]^2."""
+    hi = int(round(8 * omega))
+    return Problem(
+        net=toggle(omega), c=TOGGLE_C, x0=(0, 0), region_w=(-1, 1), region_theta=0,
+        R=R, decorr_mode=TIME, decorr=1.0, dephase_mode=TIME, dephase=1.0,
+        T=T, t_burn=T / 2.0, hist_lo=(0, 0), hist_hi=(hi, hi), rer_eps=(0.01,) * 4,
+        seed=seed, instance_id=instance_id)
+
+
+def paper_schlogl_problem(seed: int = 0, instance_id: int = 0, R: int = 100, n_c: int = 5000,
+                          n_p: int = 5000, T: float = 1e5, V: float = 25.0) -> Problem:
+    """The paper's Schloegl run: STEPS thresholds, W+ = {x <= 25.96} (Sec. IV A)."""
+    return Problem(
+        net=schlogl_paper(V), c=SCHLOGL_PAPER_C, x0=(0,), region_w=(1,), region_theta=26,
+        R=R, decorr_mode=STEPS, decorr=float(n_c), dephase_mode=STEPS, dephase=float(n_p),
+        T=T, t_burn=T / 2.0, hist_lo=(0,), hist_hi=(149,), rer_eps=(0.01,) * 4,
+        seed=seed, instance_id=instance_id)
+
+
+def c3_batch(seed: int = 0, n_schlogl: int = 128, n_toggle: int = 128,
+             r_lo: int = 64, r_hi: int = 4096, omega_lo: int = 25, omega_hi: int = 100,
+             T_schlogl: float = 200.0, T_toggle: float = 2e4) -> List[Problem]:
+    """Mixed batch: Schloegl with each c_k scaled by a log-uniform factor in [0.9, 1.1],
+    toggle with Omega uniform on {omega_lo..omega_hi}; R log-uniform on [r_lo, r_hi]."""
+    rng = np.random.default_rng(seed)
+    out: List[Problem] = []
+    for i in range(n_schlogl):
+        f = np.exp(rng.uniform(math.log(0.9), math.log(1.1), size=4))
+        R = int(round(math.exp(rng.uniform(math.log(r_lo), math.log(r_hi)))))
+        c = tuple(float(a * b) for a, b in zip(SCHLOGL_CLASSIC_C, f))
+        p = c1_schlogl(seed=0, instance_id=i, R=R, T=T_schlogl).replace(c=c)
+        out.append(p)
+    for i in range(n_toggle):
+        om = int(rng.integers(omega_lo, omega_hi + 1))
+        R = int(round(math.exp(rng.uniform(math.log(r_lo), math.log(r_hi)))))
+        out.append(c2_toggle(seed=0, instance_id=n_schlogl + i, omega=float(om), R=R, T=T_toggle))
+    return out
+
+
+def c5_requests(seed: int = 0, n: int = 64, rate: float = 10.0, r_lo: int = 256,
+                r_hi: int = 16384, omega_lo: int = 25, omega_hi: int = 150,
+                T_schlogl: float = 200.0, T_toggle: float = 2e4):
+    """Poisson request stream: returns (arrival_times, problems); 50% Schloegl with
+    perturbed c, 50% toggle; the request id is the Philox instance id."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    probs: List[Problem] = []
+    for i in range(n):
+        R = int(round(math.exp(rng.uniform(math.log(r_lo), math.log(r_hi)))))
+        if rng.uniform() < 0.5:
+            f = np.exp(rng.uniform(math.log(0.9), math.log(1.1), size=4))
+            c = tuple(float(a * b) for a, b in zip(SCHLOGL_CLASSIC_C, f))
+            probs.append(c1_schlogl(seed=seed, instance_id=i, R=R, T=T_schlogl).replace(c=c))
+        else:
+            om = int(rng.integers(omega_lo, omega_hi + 1))
+            probs.append(c2_toggle(seed=seed, instance_id=i, omega=float(om), R=R, T=T_toggle))
+    return arrivals, probs

@@ -1,0 +1,246 @@
+"""Exact laws that pin the CPU oracle (test helpers; numpy/scipy only).
+
+Nothing here calls the oracle or the GPU library.  The model propensities are
+written out again, directly from the paper's tables and the benchmark model
+definitions, so that a mistake in the oracle's factored propensity code shows
+up as a disagreement.
+
+* birth-death chains (Schloegl, Sec. IV A, is one): closed-form stationary law
+  pi(x) ~ prod_{k<=x} lam+(k-1)/lam-(k), the asymptotic variance (IAF) of
+  int f, and CME sensitivities by differentiating the closed form;
+* general CTMCs on a truncated lattice: stationary law from pi Q = 0 (eq. Q);
+* the embedded (jump) chain restricted to a metastable set W: its
+  quasi-stationary distribution nu (left Perron vector, Sec. II A) and the
+  law of X_n conditioned on N > n, which Fleming-Viot dephasing samples.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+# ----------------------------------------------------------------------------
+# Model propensities, written from the model definitions
+# ----------------------------------------------------------------------------
+
+def schlogl_classic_rates(x, c=(3e-7, 1e-4, 1e-3, 3.5), A=1e5, B=2e5):
+    """(lam1..lam4) of the classic Schloegl network at integer states x (array)."""
+    x = np.asarray(x, dtype=np.float64)
+    c1, c2, c3, c4 = c
+    l1 = c1 / 2.0 * A * x * (x - 1)
+    l2 = c2 / 6.0 * x * (x - 1) * (x - 2)
+    l3 = c3 * B * np.ones_like(x)
+    l4 = c4 * x
+    return np.clip(np.stack([l1, l2, l3, l4]), 0.0, None)
+
+
+def schlogl_paper_rates(x, c=(3.0, 0.6, 0.25, 2.95), V=25.0, a=1.0, b=2.0):
+    """Table I: c1 a x(x-1)/V, c2 x(x-1)(x-2)/V^2, c3 b V, c4 x."""
+    x = np.asarray(x, dtype=np.float64)
+    c1, c2, c3, c4 = c
+    l1 = c1 * a * x * (x - 1) / V
+    l2 = c2 * x * (x - 1) * (x - 2) / V ** 2
+    l3 = c3 * b * V * np.ones_like(x)
+    l4 = c4 * x
+    return np.clip(np.stack([l1, l2, l3, l4]), 0.0, None)
+
+
+def toggle_rates(u, v, omega, c=(3.0, 3.0, 2.0, 2.0)):
+    """Gardner toggle: Omega a1/(1+(v/Omega)^beta), u, Omega a2/(1+(u/Omega)^gamma), v."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    a1, a2, be, ga = c
+    l1 = omega * a1 / (1.0 + (v / omega) ** be)
+    l2 = u
+    l3 = omega * a2 / (1.0 + (u / omega) ** ga)
+    l4 = v
+    return np.stack([l1, l2, l3, l4])
+
+
+TOGGLE_STOICH = ((1, 0), (-1, 0), (0, 1), (0, -1))
+
+
+# ----------------------------------------------------------------------------
+# Birth-death chains
+# ----------------------------------------------------------------------------
+
+def birth_death_pi(lp: np.ndarray, lm: np.ndarray) -> np.ndarray:
+    """Stationary law on {0..N} of a birth-death chain with birth rates lp[x]
+    and death rates lm[x] (lm[0] ignored): pi(x) ~ prod_{k=1}^x lp[k-1]/lm[k]."""
+    N = len(lp) - 1
+    logw = np.zeros(N + 1)
+    for x in range(1, N + 1):
+        logw[x] = logw[x - 1] + math.log(lp[x - 1]) - math.log(lm[x])
+    logw -= logw.max()
+    w = np.exp(logw)
+    return w / w.sum()
+
+
+def schlogl_classic_pi(N=1000, c=(3e-7, 1e-4, 1e-3, 3.5)):
+    x = np.arange(N + 1)
+    l = schlogl_classic_rates(x, c)
+    return birth_death_pi(l[0] + l[2], l[1] + l[3])
+
+
+def schlogl_paper_pi(N=400, c=(3.0, 0.6, 0.25, 2.95), V=25.0):
+    x = np.arange(N + 1)
+    l = schlogl_paper_rates(x, c, V)
+    return birth_death_pi(l[0] + l[2], l[1] + l[3])
+
+
+def birth_death_iaf(pi: np.ndarray, lp: np.ndarray, f: np.ndarray) -> float:
+    """Asymptotic variance lim Var(int_0^T f)/T of a birth-death chain:
+    2 sum_x G(x)^2 / (pi(x) lp(x)), G(x) = sum_{y<=x} pi(y)(f(y) - pi f).
+    G is summed from the nearer tail (G(x) = -sum_{y>x}...) to avoid cancellation."""
+    pf = float(np.dot(pi, f))
+    d = pi * (f - pf)
+    G_lo = np.cumsum(d)
+    G_hi = -(np.cumsum(d[::-1])[::-1] - d)
+    G = np.where(np.arange(len(pi)) < len(pi) // 2, G_lo, G_hi)
+    m = pi[:-1] * lp[:-1] > 0
+    return float(2.0 * np.sum(G[:-1][m] ** 2 / (pi[:-1][m] * lp[:-1][m])))
+
+
+def schlogl_paper_mean(c, V=25.0, N=400):
+    pi = schlogl_paper_pi(N, c, V)
+    return float(np.dot(pi, np.arange(N + 1)))
+
+
+def schlogl_paper_sensitivity(k: int, V=25.0, h=1e-6, N=400):
+    """d E_pi[x] / d c_k by a central difference of the closed-form law."""
+    c = np.array((3.0, 0.6, 0.25, 2.95))
+    cp, cm = c.copy(), c.copy()
+    cp[k] *= 1 + h
+    cm[k] *= 1 - h
+    return (schlogl_paper_mean(cp, V, N) - schlogl_paper_mean(cm, V, N)) / (2 * h * c[k])
+
+
+def schlogl_rre_roots(c=(3.0, 0.6, 0.25, 2.95), a=1.0, b=2.0):
+    """Roots of the RRE right-hand side c1 a x^2 - c2 x^3 + c3 b - c4 x (Sec. IV A)."""
+    c1, c2, c3, c4 = c
+    r = np.roots([-c2, c1 * a, -c4, c3 * b])
+    return np.sort(r[np.abs(r.imag) < 1e-9].real)
+
+
+# ----------------------------------------------------------------------------
+# Truncated lattices
+# ----------------------------------------------------------------------------
+
+class Lattice:
+    """States of a truncated 2-D lattice [0,N]^2 with reflecting truncation
+    (transitions leaving the box are dropped)."""
+
+    def __init__(self, N: int):
+        self.N = N
+        self.n = (N + 1) ** 2
+
+    def idx(self, u, v):
+        return u * (self.N + 1) + v
+
+    def states(self):
+        g = np.arange(self.N + 1)
+        U, V = np.meshgrid(g, g, indexing="ij")
+        return U.ravel(), V.ravel()
+
+
+def toggle_generator(omega, N, c=(3.0, 3.0, 2.0, 2.0)):
+    L = Lattice(N)
+    U, V = L.states()
+    lam = toggle_rates(U, V, omega, c)
+    rows, cols, vals = [], [], []
+    for j, (du, dv) in enumerate(TOGGLE_STOICH):
+        u2, v2 = U + du, V + dv
+        ok = (u2 >= 0) & (u2 <= N) & (v2 >= 0) & (v2 <= N) & (lam[j] > 0)
+        src = L.idx(U[ok], V[ok])
+        dst = L.idx(u2[ok], v2[ok])
+        rows.append(src)
+        cols.append(dst)
+        vals.append(lam[j][ok])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    Q = sp.coo_matrix((vals, (rows, cols)), shape=(L.n, L.n)).tocsr()
+    out = np.asarray(Q.sum(axis=1)).ravel()
+    Q = Q - sp.diags(out)
+    return L, Q.tocsr()
+
+
+def stationary_from_generator(Q: sp.csr_matrix) -> np.ndarray:
+    """Solve pi Q = 0, sum pi = 1 by replacing one balance equation."""
+    n = Q.shape[0]
+    A = Q.T.tolil()
+    A[0, :] = np.ones(n)
+    b = np.zeros(n)
+    b[0] = 1.0
+    pi = spla.spsolve(A.tocsc(), b)
+    pi = np.clip(pi, 0.0, None)
+    return pi / pi.sum()
+
+
+def toggle_pi(omega, N, c=(3.0, 3.0, 2.0, 2.0)):
+    L, Q = toggle_generator(omega, N, c)
+    return L, stationary_from_generator(Q).reshape(N + 1, N + 1)
+
+
+def toggle_fim_exact(omega, N, c=(3.0, 3.0, 2.0, 2.0)):
+    """E_pi[sum_j lam_j grad log lam_j grad log lam_j^T] w.r.t. (a1, a2, beta, gamma)."""
+    L, pi = toggle_pi(omega, N, c)
+    U, V = L.states()
+    F = toggle_fim_integrand(U, V, omega, c)
+    return np.einsum("s,sab->ab", pi.ravel(), F)
+
+
+def toggle_fim_integrand(U, V, omega, c=(3.0, 3.0, 2.0, 2.0)):
+    """Per-state FIM integrand of the toggle, (S, 4, 4)."""
+    a1, a2, be, ga = c
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    lam = toggle_rates(U, V, omega, c)
+    yv, yu = V / omega, U / omega
+    qv, qu = yv ** be, yu ** ga
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dbeta = np.where(yv > 0, -qv * np.log(np.where(yv > 0, yv, 1.0)) / (1 + qv), 0.0)
+        dgam = np.where(yu > 0, -qu * np.log(np.where(yu > 0, yu, 1.0)) / (1 + qu), 0.0)
+    g1 = np.stack([1 / a1 * np.ones_like(U), 0 * U, dbeta, 0 * U], axis=1)
+    g3 = np.stack([0 * U, 1 / a2 * np.ones_like(U), 0 * U, dgam], axis=1)
+    return (lam[0][:, None, None] * g1[:, :, None] * g1[:, None, :]
+            + lam[2][:, None, None] * g3[:, :, None] * g3[:, None, :])
+
+
+# ----------------------------------------------------------------------------
+# Embedded chain on a metastable set
+# ----------------------------------------------------------------------------
+
+def embedded_substochastic(L: Lattice, Q: sp.csr_matrix, in_W: np.ndarray):
+    """Jump-chain transition matrix restricted to W (rows of W, columns of W)."""
+    out = -Q.diagonal()
+    P = sp.diags(1.0 / np.where(out > 0, out, 1.0)) @ (Q + sp.diags(out))
+    Wi = np.flatnonzero(in_W)
+    return P.tocsr()[Wi][:, Wi].tocsr(), Wi
+
+
+def qsd_embedded(PW: sp.csr_matrix):
+    """Left Perron vector nu (nu P_W = rho nu) and rho of the embedded chain on W."""
+    vals, vecs = spla.eigs(PW.T.tocsc(), k=4, which="LR")
+    i = int(np.argmax(vals.real))
+    rho = float(vals[i].real)
+    nu = np.abs(vecs[:, i].real)
+    return nu / nu.sum(), rho
+
+
+def conditioned_law(PW: sp.csr_matrix, start: int, n: int) -> np.ndarray:
+    """Law of X_n given no exit from W by step n, starting at W-index start."""
+    mu = np.zeros(PW.shape[0])
+    mu[start] = 1.0
+    PT = PW.T.tocsr()
+    for _ in range(n):
+        mu = PT @ mu
+        mu /= mu.sum()
+    return mu
+
+
+def tv(p: np.ndarray, q: np.ndarray) -> float:
+    return 0.5 * float(np.abs(np.asarray(p, dtype=float) - np.asarray(q, dtype=float)).sum())
