@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark the ParRep hot path on one MI355X.
+
+Workload (one step): a batch of independent ParRep trajectories of the
+two-gene toggle switch (Omega = 50, a1 = a2 = 3, beta = gamma = 2, R = 1024
+replicas, t_c = t_p = 1.0 time units, horizon T = 2e4, burn-in T/2, 2-D
+stationary histogram over [0,400]^2, FIM and RER w.r.t. (a1, a2, beta, gamma)),
+seeds = instance ids, all inputs synthetic.  The paper estimates its
+stationary and sensitivity quantities from many independent trajectories, so
+a step solves a batch of them in one launch.
+
+Prints one JSON line: SSA events/s (all events the method executes:
+decorrelation + dephasing + credited and discarded parallel-step events),
+the instance kernel's roofline position (VALU-issue bound), and the CPU
+oracle timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SSA events/s on 1 GPU (% VALU peak); batched/served ParRep solves/s + p50/p99"
+
+# VALU issue model of one toggle-switch SSA event (derived in the design doc):
+# lane-op slots per event at CDNA issue cost.
+VALU_SLOTS_PER_EVENT = 238
+# MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz, a wave64 VALU op takes 4 cycles
+# -> 256*4*16*2.4e9 = 3.93e13 lane-op slots per second.
+VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds: float, threads: int, T_sample: float):
+    """Time the CPU oracle (as it stands) on toggle trajectories of the same
+    problem with the horizon cut to T_sample, one trajectory per thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import build as ob
+    ob.build(force=False)
+    from oracle import oracle as O
+    from paper_1705_06807_amd import workloads as W
+
+    def one(i):
+        p = W.c2_toggle(seed=0, instance_id=100000 + i, T=T_sample)
+        return O.run(p, cycle_log_cap=0).events
+
+    events = 0
+    n = 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        while time.perf_counter() - t0 < seconds:
+            events += sum(ex.map(one, range(n, n + threads)))
+            n += threads
+    dt = time.perf_counter() - t0
+    return {"value": events / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": "%d toggle trajectories (Omega=50, R=1024, t_c=t_p=1) with T cut to %g, "
+                      "%d threads, %.1f s wall" % (n, T_sample, threads, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=512,
+                    help="independent trajectories per step")
+    ap.add_argument("--T", type=float, default=2e4)
+    ap.add_argument("--rpl", type=int, default=0, help="replicas per lane (0 = library choice)")
+    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = library)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-T", type=float, default=1000.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs each ParRep instance on a single "
+              "device and has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1705_06807_amd import binding as B
+    from paper_1705_06807_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    B.lib()
+    ctx = B.context(0)
+    probs = [W.c2_toggle(seed=0, instance_id=i, T=args.T) for i in range(args.instances)]
+    outs = [B.Outputs(ctx, p, cycle_log_cap=0) for p in probs]
+    ev_b = torch.cuda.Event(enable_timing=True)
+    ev_a = torch.cuda.Event(enable_timing=True)
+    ev_b.record()
+    ev_a.record()
+    torch.cuda.synchronize()
+
+    def step(events=None):
+        B.parrep_solve_batch(probs, ctx=ctx, replicas_per_lane=args.rpl, waves=args.waves,
+                             outputs=outs, events=events)
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log("warmup %d: %.3f s" % (i, time.perf_counter() - t))
+
+    kernel_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events=(ev_b, ev_a))
+        ev_a.synchronize()
+        kernel_ms.append(ev_b.elapsed_time(ev_a))
+        log("step %d: instance kernel %.1f ms" % (i, kernel_ms[-1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    counters = torch.stack([o.counters for o in outs]).cpu()
+    ev = counters[:, 0:4].sum().item()          # decorr + dephase + credited + discarded
+    per_phase = {k: int(counters[:, j].sum().item()) for j, k in enumerate(
+        ("ev_decorr", "ev_dephase", "ev_par_credited", "ev_par_discarded", "cycles"))}
+    t_end = torch.stack([o.stats[0] for o in outs]).cpu()
+    ok = bool((counters[:, 7] == 0).all().item()) and bool((t_end == args.T).all().item())
+
+    ms_per_step = 1e3 * wall / args.steps
+    value = ev / (wall / args.steps)
+    k_avg = sum(kernel_ms) / len(kernel_ms)
+    achieved = ev * VALU_SLOTS_PER_EVENT / (k_avg * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "toggle switch Omega=50 (a1=a2=3, beta=gamma=2), R=1024, "
+                        "t_c=t_p=1.0, T=%g, burn-in T/2, hist [0,400]^2, FIM+RER(a1,a2,beta,gamma); "
+                        "%d independent trajectories per step" % (args.T, args.instances),
+            "instances": args.instances,
+            "replicas": 1024,
+            "horizon": args.T,
+        },
+        "solves_per_s": args.instances / (wall / args.steps),
+        "events_per_step": ev,
+        "events_by_phase": per_phase,
+        "all_runs_reached_T": ok,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_instance",
+            "achieved": achieved / 1e12,
+            "peak": VALU_PEAK_SLOTS / 1e12,
+            "unit": "T VALU lane-op/s (issue slots)",
+            "frac": achieved / VALU_PEAK_SLOTS,
+            "traffic": None,
+            "kernel_ms": k_avg,
+            "ops_per_event": VALU_SLOTS_PER_EVENT,
+        },
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log("cpu baseline: %d threads, ~%.0f s" % (threads, args.cpu_seconds))
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, threads, args.cpu_T)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

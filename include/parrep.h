@@ -1,0 +1,230 @@
+/*
+ * parrep.h -- C ABI of libparrep: parallel replica dynamics (ParRep) for
+ * bistable continuous-time Markov chain reaction networks on AMD MI355X.
+ *
+ * Method: Wang & Plechac, "Parallel replica dynamics method for bistable
+ * stochastic reaction networks: simulation and sensitivity analysis"
+ * (arXiv 1705.06807).  One solve runs Algorithm 1 (Sec. II A): serial
+ * decorrelation, Fleming-Viot dephasing of R replicas, and the parallel step
+ * whose first exit is credited by the ParRep-CTMC rule, cycling until the
+ * ParRep clock reaches the horizon T.  Along the way it accumulates the
+ * time-weighted stationary histogram (the ergodic average of Sec. I A) and
+ * the path-space Fisher information and relative entropy rate integrands
+ * (Sec. III, Appendix A) over the window [t_burn, T].
+ *
+ * All compute runs in HIP kernels for gfx950.  Conventions shared by every
+ * entry point:
+ *   - Pointers named "device" are HIP device pointers owned by the caller;
+ *     pointers named "host" are read during the call only.
+ *   - Calls that take a stream enqueue work on it and return without
+ *     waiting; outputs are valid after the stream has been synchronised.
+ *   - Functions return PARREP_OK or a negative parrep_status;
+ *     parrep_last_error() gives a message for the calling thread.  No C++
+ *     exception crosses this interface.
+ *   - Random numbers: Philox4x32-10 with key (seed, instance_id) and counter
+ *     (step, replica, cycle, phase tag << 28 | step >> 32); one block per SSA
+ *     event.  Two solves with equal inputs give equal integer results.
+ */
+#ifndef PARREP_H
+#define PARREP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PARREP_MAX_SPECIES 4
+#define PARREP_MAX_REACTIONS 8
+#define PARREP_MAX_FACTORS 2
+#define PARREP_MAX_PARAMS 8
+#define PARREP_MAX_REPLICAS 16384
+#define PARREP_NCOUNTERS 12
+#define PARREP_CYCLE_REC 12
+#define PARREP_NSTATS 80
+
+typedef enum {
+    PARREP_OK = 0,
+    PARREP_EINVAL = -1,       /* an argument is out of range or inconsistent   */
+    PARREP_ENOMEM = -2,       /* device or host allocation failed               */
+    PARREP_EDEVICE = -3,      /* a HIP call failed                              */
+    PARREP_EUNSUPPORTED = -4, /* valid input this build does not handle         */
+    PARREP_EBUSY = -5,        /* result not ready yet (server poll)             */
+    PARREP_ECANCELLED = -6    /* request was cancelled                          */
+} parrep_status;
+
+/* Propensity factor kinds.  A reaction's propensity (Sec. I A) is
+ *   lambda_j(x) = k_j * phi_1(x) * phi_2(x) * ...   (multiplied left to right)
+ *   k_j = c[rate_param] * kappa   (k_j = kappa when rate_param < 0)
+ * PARREP_FALLING:  phi = x_s (x_s-1) ... (x_s-order+1)    (mass action)
+ * PARREP_HILL_REP: phi = 1 / (1 + (x_s / K)^c[hill_param]) (repression)  */
+enum { PARREP_FALLING = 0, PARREP_HILL_REP = 1 };
+
+/* Threshold units for decorrelation and dephasing: PARREP_STEPS counts
+ * transitions (the paper's n_c, n_p); PARREP_TIME uses simulated time. */
+enum { PARREP_STEPS = 0, PARREP_TIME = 1 };
+
+/* counters[] slots of a result */
+enum {
+    PARREP_CNT_EV_DECORR = 0,        /* decorrelation events (all credited)        */
+    PARREP_CNT_EV_DEPHASE = 1,       /* dephasing events                           */
+    PARREP_CNT_EV_PAR_CREDITED = 2,  /* parallel-step events credited              */
+    PARREP_CNT_EV_PAR_DISCARDED = 3, /* drawn in a last round but not credited     */
+    PARREP_CNT_CYCLES = 4,           /* parallel steps that ended with an exit     */
+    PARREP_CNT_S3_ROUNDS = 5,
+    PARREP_CNT_S2_ROUNDS = 6,
+    PARREP_CNT_STATUS = 7,           /* 0 horizon reached, 1 event budget hit, 2 aborted */
+    PARREP_CNT_FV_RESTARTS = 8,
+    PARREP_CNT_END_PHASE = 9,        /* 1 horizon in decorrelation, 3 in parallel step, 9 stopped */
+    PARREP_CNT_N_CYCLE_LOG = 10      /* cycle records produced (may exceed the capacity) */
+};
+
+/* stats[] layout of a result (PARREP_NSTATS doubles) */
+enum {
+    PARREP_ST_T = 0,            /* ParRep clock at the end (= T unless stopped)            */
+    PARREP_ST_OUTSIDE = 1,      /* time outside the histogram box, over [0, T]             */
+    PARREP_ST_OUTSIDE_W = 2,    /* the same over [t_burn, T]                               */
+    PARREP_ST_FIM = 3,          /* n_params x n_params, row-major: (1/(T-t_burn)) int FIM  */
+    PARREP_ST_RER = 67,         /* n_params: (1/(T-t_burn)) int RER integrand, c_k*(1+eps_k) */
+    PARREP_ST_Y = 75            /* n_species: int_{t_burn}^T x_i ds                          */
+};
+
+typedef struct parrep_ctx parrep_ctx;
+typedef struct parrep_net parrep_net;
+
+typedef struct {
+    int32_t kind;        /* PARREP_FALLING or PARREP_HILL_REP                      */
+    int32_t species;     /* species index the factor reads                          */
+    int32_t order;       /* falling-factorial order (0..8)                          */
+    int32_t hill_param;  /* Hill only: index of the exponent in c                   */
+    double K;            /* Hill only: scale (> 0)                                   */
+} parrep_factor;
+
+typedef struct {
+    int32_t rate_param;  /* index into c, or -1 for a fixed rate kappa              */
+    int32_t n_factors;   /* 0..PARREP_MAX_FACTORS                                   */
+    double kappa;        /* >= 0                                                     */
+    int32_t stoich[PARREP_MAX_SPECIES];  /* net change eta_j: produced - consumed   */
+    parrep_factor factor[PARREP_MAX_FACTORS];
+} parrep_reaction;
+
+/* The problem statement of one solve (Sec. II A, Alg. 1; Sec. IV for T and
+ * the burn-in).  Unused array tails are ignored. */
+typedef struct {
+    double c[PARREP_MAX_PARAMS];         /* rate vector c (finite, >= 0)                 */
+    double rer_eps[PARREP_MAX_PARAMS];   /* relative perturbation per parameter for RER  */
+    int32_t use_rer;                     /* 0: RER outputs are zero                      */
+    int32_t x0[PARREP_MAX_SPECIES];      /* initial population                           */
+    int32_t region_w[PARREP_MAX_SPECIES];/* metastable sets: set 1 = {w.x >= theta},    */
+    int64_t region_theta;                /*                   set 0 = {w.x <  theta}     */
+    int32_t R;                           /* replicas, 1..PARREP_MAX_REPLICAS             */
+    int32_t decorr_mode;                 /* PARREP_STEPS (n_c) or PARREP_TIME (t_c)      */
+    double decorr;
+    int32_t dephase_mode;                /* PARREP_STEPS (n_p) or PARREP_TIME (t_p)      */
+    double dephase;
+    double T;                            /* horizon, 0 < T < 2^51                        */
+    double t_burn;                       /* window start for FIM/RER/Y, 0 <= t_burn < T  */
+    int32_t hist_lo[PARREP_MAX_SPECIES]; /* histogram box, inclusive, unit bins,         */
+    int32_t hist_hi[PARREP_MAX_SPECIES]; /* row-major with species 0 slowest             */
+    uint32_t seed;                       /* Philox key word 0                            */
+    uint32_t instance_id;                /* Philox key word 1                            */
+    int64_t max_events;                  /* event budget, <= 0: 2^50                     */
+} parrep_problem;
+
+/* Caller-owned device buffers that receive one solve's outputs. */
+typedef struct {
+    double* hist;         /* device, nbins: time per state over [0, T]          (required) */
+    double* hist_window;  /* device, nbins: time per state over [t_burn, T]     (required) */
+    double* stats;        /* device, PARREP_NSTATS doubles (see PARREP_ST_*)     (required) */
+    int32_t* x_final;     /* device, PARREP_MAX_SPECIES: state whose holding interval holds T */
+    int64_t* counters;    /* device, PARREP_NCOUNTERS                            (required) */
+    int64_t* cycle_log;   /* device, cycle_log_cap * PARREP_CYCLE_REC, or NULL: per cycle
+                             {cycle, S1 events, S2 rounds, S3 rounds, K (0: no exit),
+                              end phase, state after the cycle[4], 0, 0}               */
+    int32_t cycle_log_cap;
+    int32_t reserved;
+} parrep_result;
+
+/* Launch shape for the batched solve: replicas per lane and waves per
+ * workgroup (0 = let the library choose from the replica count), and two
+ * optional hipEvent_t handles (NULL = none) recorded on the stream right
+ * before and right after the instance kernel, so a caller can time it. */
+typedef struct {
+    int32_t replicas_per_lane;  /* 1, 4 or 16                                        */
+    int32_t waves;              /* 1, 4 or 16 (64-lane wavefronts per workgroup)      */
+    void* event_before;         /* hipEvent_t or NULL                                 */
+    void* event_after;          /* hipEvent_t or NULL                                 */
+} parrep_launch;
+
+/* Create a context on a HIP device: it owns the scratch arena and the
+ * compiled kernels.  EDEVICE if the device cannot be used. */
+int parrep_ctx_create(int device, parrep_ctx** out);
+void parrep_ctx_destroy(parrep_ctx* ctx);
+
+/* Thread-local message for the last failing call of this thread. */
+const char* parrep_last_error(void);
+
+/* Define a reaction network (Sec. I A): n_species <= 4, n_reactions <= 8,
+ * n_params <= 8, reactions rx[n_reactions] read during the call (host).
+ * EINVAL when an index is out of range, an order exceeds 8, K <= 0 or kappa
+ * is negative or not finite. */
+int parrep_net_create(parrep_ctx* ctx, int32_t n_species, int32_t n_reactions, int32_t n_params,
+                      const parrep_reaction* rx, parrep_net** out);
+void parrep_net_destroy(parrep_net* net);
+
+/* Number of histogram bins the problem asks for (host arithmetic only);
+ * negative on invalid boxes. */
+int64_t parrep_problem_nbins(const parrep_net* net, const parrep_problem* prob);
+
+/* One ParRep solve (Alg. 1 from x0 until the clock reaches T), enqueued on
+ * stream (a hipStream_t; NULL = the null stream).  prob is host memory read
+ * during the call; res holds caller-owned device buffers.  EINVAL on
+ * inconsistent input (validated before anything is enqueued). */
+int parrep_solve(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
+                 const parrep_result* res, void* stream);
+
+/* Many independent solves in one launch: count instances, nets[i] and
+ * probs[i] (host arrays), res[i] (host array of device-buffer descriptors).
+ * Each instance's outputs equal its parrep_solve outputs for any launch
+ * shape (integers exactly; floats up to summation order).  launch may be NULL. */
+int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* nets,
+                       const parrep_problem* probs, const parrep_result* res,
+                       const parrep_launch* launch, void* stream);
+
+/* Test hook: Philox4x32-10 blocks.  ctr_key (device, n x 6 uint32:
+ * counter words 0-3 then key words 0-1) -> out (device, n x 4 uint32). */
+int parrep_philox(parrep_ctx* ctx, int64_t n, const uint32_t* ctr_key, uint32_t* out,
+                  void* stream);
+
+/* Test hook: one SSA event (Sec. I A; the "generate tau and J" step of Alg. 1)
+ * per row: states (device, n x PARREP_MAX_SPECIES int32), blocks (device,
+ * n x 4 uint32 Philox words) -> a0 (device, n), tau (device, n; +inf when
+ * absorbing), J (device, n; -1 when absorbing). */
+int parrep_events(parrep_ctx* ctx, const parrep_net* net, const double* c_host, int64_t n,
+                  const int32_t* states, const uint32_t* blocks, double* a0, double* tau,
+                  int32_t* J, void* stream);
+
+/* Test hook: the dephasing step alone (Sec. II A, Alg. 1) from state xt
+ * (host, n_species), in the set of xt, with prob's replica count, dephasing
+ * threshold and key, at cycle index `cycle`.  Y_out (device, R x
+ * PARREP_MAX_SPECIES int32) receives the replica states; rounds_out (device,
+ * one int64) the number of rounds. */
+int parrep_dephase_only(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
+                        const int32_t* xt, uint32_t cycle, int32_t* Y_out, int64_t* rounds_out,
+                        void* stream);
+
+/* Test hook: the parallel step alone (Sec. II A, Alg. 1) from replica states
+ * init (device, R x PARREP_MAX_SPECIES int32, all in the set of replica 0),
+ * without a horizon, for at most max_rounds rounds (< 0: no limit).
+ * out_i64 (device, 2): {N*, K} ({-1, 0} if the round limit came first);
+ * exit_state (device, PARREP_MAX_SPECIES); credited (device, 1 double):
+ * the credited time sum_{keys <= R(N*-1)+K} tau. */
+int parrep_parallel_only(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
+                         const int32_t* init, uint32_t cycle, int64_t max_rounds,
+                         int64_t* out_i64, int32_t* exit_state, double* credited, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,992 @@
+// parrep_device.h -- device code of libparrep for gfx950: parallel replica dynamics
+// (Wang & Plechac, arXiv 1705.06807, Sec. II A, Algorithm 1) on CTMC
+// reaction networks.
+//
+// One workgroup runs one ParRep instance.  Its replicas are spread over the
+// lanes: replica r = k*B + tid lives in register slot k of thread tid
+// (B = 64*WAVES threads, RPL slots).  Decorrelation is serial and runs on
+// thread 0; dephasing and the parallel step advance all replicas one SSA
+// event per round.  Per round the workgroup only exchanges what the method
+// needs: whether any replica left the metastable set (dephasing), the first
+// exiting replica and the credited time (parallel step).  Everything rare --
+// Fleming-Viot restarts, the round that crosses the burn-in time or the
+// horizon, the exit round -- takes a slower exact path.
+//
+// Numerics shared with the CPU oracle by definition, not by code:
+//   * Philox4x32-10, key (seed, instance), counter (step, replica, cycle,
+//     tag<<28 | step>>32); u_open from words 0-1 in (0,1], u_sel from words
+//     2-3 in [0,1);
+//   * propensities k_j * phi_1 * phi_2 left to right, falling factorials
+//     exact in 64-bit integers, Hill powers by repeated multiplication for
+//     integral exponents; tau = -log(u_open)/a0; J = first j with
+//     u_sel*a0 < S_j; everything built with -ffp-contract=off;
+//   * the ParRep clock is an exact 64.64 fixed-point sum of credited
+//     holding times (each truncated to 2^-64), so the burn-in time and the
+//     horizon are crossed at one event whatever the reduction order.
+#pragma once
+#include "parrep_internal.h"
+
+#include <climits>
+
+namespace parrep {
+namespace dev {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+struct Blk {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Blk philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Blk{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ Blk draw(uint64_t step, uint32_t rep, uint32_t cycle, uint32_t tag,
+                                    uint32_t k0, uint32_t k1) {
+    return philox10((uint32_t)step, rep, cycle,
+                    (tag << 28) | ((uint32_t)(step >> 32) & 0x0FFFFFFFu), k0, k1);
+}
+
+__device__ __forceinline__ double u_open(const Blk& b) {
+    const uint64_t w = ((uint64_t)b.w1 << 32) | b.w0;
+    return (double)((w >> 11) + 1) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ double u_sel(const Blk& b) {
+    const uint64_t w = ((uint64_t)b.w3 << 32) | b.w2;
+    return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------------------
+// 64.64 fixed-point clock
+// ---------------------------------------------------------------------------
+struct Fx {
+    uint64_t hi, lo;
+};
+
+__device__ __forceinline__ Fx fx_add(Fx a, Fx b) {
+    Fx r;
+    r.lo = a.lo + b.lo;
+    r.hi = a.hi + b.hi + (r.lo < a.lo ? 1u : 0u);
+    return r;
+}
+__device__ __forceinline__ Fx fx_sub(Fx a, Fx b) {
+    Fx r;
+    r.lo = a.lo - b.lo;
+    r.hi = a.hi - b.hi - (a.lo < b.lo ? 1u : 0u);
+    return r;
+}
+__device__ __forceinline__ bool fx_ge(Fx a, Fx b) {
+    return a.hi > b.hi || (a.hi == b.hi && a.lo >= b.lo);
+}
+__device__ __forceinline__ bool fx_gt(Fx a, Fx b) { return !fx_ge(b, a); }
+
+// Correctly rounded uint64 -> double: both halves are exact, one rounding in the sum.
+__device__ __forceinline__ double u64_to_f64(uint64_t v) {
+    return (double)(uint32_t)(v >> 32) * 0x1.0p32 + (double)(uint32_t)v;
+}
+__device__ __forceinline__ double fx_to_f64(Fx v) {
+    return u64_to_f64(v.hi) + u64_to_f64(v.lo) * 0x1.0p-64;
+}
+
+// floor(d * 2^64) for 0 <= d < 2^52, by exact steps; +inf and larger saturate.
+__device__ __forceinline__ Fx fx_from(double d) {
+    if (!(d < 0x1.0p52)) return Fx{1ull << 52, 0};
+    if (!(d > 0.0)) return Fx{0, 0};
+    const double ip = floor(d);
+    const double a = (d - ip) * 0x1.0p32;
+    const double ah = floor(a);
+    const double b = (a - ah) * 0x1.0p32;
+    const double bl = floor(b);
+    const double iph = floor(ip * 0x1.0p-32);
+    const double ipl = ip - iph * 0x1.0p32;
+    Fx r;
+    r.hi = ((uint64_t)(uint32_t)iph << 32) | (uint64_t)(uint32_t)ipl;
+    r.lo = ((uint64_t)(uint32_t)ah << 32) | (uint64_t)(uint32_t)bl;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Network program in LDS
+// ---------------------------------------------------------------------------
+struct SNet {
+    int32_t m, n, np, R;
+    int32_t nf[kMaxM];
+    int32_t fkind[kMaxM][kMaxF], fsp[kMaxM][kMaxF], ford[kMaxM][kMaxF];
+    int32_t fhint[kMaxM][kMaxF], fhp[kMaxM][kMaxF];
+    int32_t rate_param[kMaxM];
+    int32_t stoich[kMaxM][kMaxS];
+    int32_t rw[kMaxS];
+    int32_t hist_lo[kMaxS], hist_nb[kMaxS];
+    int32_t use_rer, pad;
+    int64_t theta;
+    int64_t hist_stride[kMaxS];
+    double k[kMaxM];
+    double kappa[kMaxM];
+    double fK[kMaxM][kMaxF];
+    double c[kMaxP], ceps[kMaxP];
+};
+
+__device__ __forceinline__ int small_int_exponent(double h) {
+    return (h >= 0.0 && h <= 64.0 && h == floor(h)) ? (int)h : -1;
+}
+
+__device__ void load_net(SNet& S, const DevInst* I) {
+    const DevNet& N = I->net;
+    S.m = N.n_reactions;
+    S.n = N.n_species;
+    S.np = N.n_params;
+    S.R = I->R;
+    S.use_rer = I->use_rer;
+    S.theta = I->region_theta;
+    for (int p = 0; p < kMaxP; ++p) {
+        S.c[p] = I->c[p];
+        S.ceps[p] = I->c[p] * (1.0 + I->rer_eps[p]);
+    }
+    for (int i = 0; i < kMaxS; ++i) {
+        S.rw[i] = I->region_w[i];
+        S.hist_lo[i] = I->hist_lo[i];
+        S.hist_nb[i] = I->hist_nb[i];
+        S.hist_stride[i] = I->hist_stride[i];
+    }
+    for (int j = 0; j < kMaxM; ++j) {
+        const DevReaction& rx = N.rx[j];
+        const bool on = j < N.n_reactions;
+        S.nf[j] = on ? rx.n_factors : 0;
+        S.rate_param[j] = rx.rate_param;
+        S.kappa[j] = rx.kappa;
+        S.k[j] = rx.rate_param >= 0 ? I->c[rx.rate_param] * rx.kappa : rx.kappa;
+        for (int i = 0; i < kMaxS; ++i) S.stoich[j][i] = rx.stoich[i];
+        for (int f = 0; f < kMaxF; ++f) {
+            S.fkind[j][f] = rx.f[f].kind;
+            S.fsp[j][f] = rx.f[f].species;
+            S.ford[j][f] = rx.f[f].order;
+            S.fhp[j][f] = rx.f[f].hill_param;
+            S.fK[j][f] = rx.f[f].K;
+            S.fhint[j][f] = (rx.f[f].kind == PARREP_HILL_REP && f < S.nf[j])
+                                ? small_int_exponent(I->c[rx.f[f].hill_param])
+                                : 0;
+        }
+    }
+}
+
+template <int NS>
+__device__ __forceinline__ int pick(const int (&x)[NS], int s) {
+    int v = x[0];
+#pragma unroll
+    for (int i = 1; i < NS; ++i)
+        if (s == i) v = x[i];
+    return v;
+}
+
+__device__ __forceinline__ double hill_pow(double y, int hint, double h) {
+    if (hint < 0) return pow(y, h);
+    if (hint == 0) return 1.0;
+    double q = y;
+    for (int i = 1; i < hint; ++i) q = q * y;
+    return q;
+}
+
+__device__ __forceinline__ double falling(int64_t xs, int order) {
+    int64_t p = 1;
+    for (int i = 0; i < order; ++i) {
+        const int64_t t = xs - i;
+        if (t <= 0) return 0.0;
+        p *= t;
+    }
+    return (double)p;
+}
+
+// phi of factor f of reaction j at species value xs (main path: exponents from c).
+__device__ __forceinline__ double factor_val(const SNet& S, int j, int f, int xs) {
+    if (S.fkind[j][f] == PARREP_FALLING) return falling(xs, S.ford[j][f]);
+    const double y = (double)xs / S.fK[j][f];
+    const double q = hill_pow(y, S.fhint[j][f], S.c[S.fhp[j][f]]);
+    return 1.0 / (1.0 + q);
+}
+
+// lambda_j(x) with an arbitrary parameter vector cv (RER perturbations).
+template <int NS>
+__device__ double prop_with(const SNet& S, int j, const int (&x)[NS], const double* cv) {
+    const int rp = S.rate_param[j];
+    double lam = rp >= 0 ? cv[rp] * S.kappa[j] : S.kappa[j];
+    for (int f = 0; f < S.nf[j]; ++f) {
+        const int xs = pick<NS>(x, S.fsp[j][f]);
+        double phi;
+        if (S.fkind[j][f] == PARREP_FALLING) {
+            phi = falling(xs, S.ford[j][f]);
+        } else {
+            const double h = cv[S.fhp[j][f]];
+            const double y = (double)xs / S.fK[j][f];
+            phi = 1.0 / (1.0 + hill_pow(y, small_int_exponent(h), h));
+        }
+        lam = lam * phi;
+    }
+    return lam;
+}
+
+// One Gillespie event at x: holding time tau (+inf if absorbing) and channel J (-1).
+template <int NS>
+__device__ __forceinline__ void ssa_event(const SNet& S, const int (&x)[NS], const Blk& b,
+                                          double& tau, int& J, double& a0) {
+    double cum[kMaxM];
+    double s = 0.0;
+    uint32_t pos = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j) {
+        cum[j] = 0.0;
+        if (j < S.m) {
+            double lam = S.k[j];
+            const int nf = S.nf[j];
+            for (int f = 0; f < nf; ++f) lam = lam * factor_val(S, j, f, pick<NS>(x, S.fsp[j][f]));
+            if (lam > 0.0) pos |= 1u << j;
+            s = s + lam;
+            cum[j] = s;
+        }
+    }
+    a0 = s;
+    if (!(s > 0.0)) {
+        tau = __builtin_inf();
+        J = -1;
+        return;
+    }
+    tau = (-log(u_open(b))) / s;
+    const double t = u_sel(b) * s;
+    int pj = -1;
+#pragma unroll
+    for (int j = kMaxM - 1; j >= 0; --j)
+        if (j < S.m && t < cum[j]) pj = j;
+    if (pj < 0) pj = 31 - __clz(pos);  // only for non-finite a0: last positive channel
+    J = pj;
+}
+
+template <int NS>
+__device__ __forceinline__ void apply_jump(const SNet& S, int (&x)[NS], int J) {
+    if (J < 0) return;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] += S.stoich[J][i];
+}
+
+template <int NS>
+__device__ __forceinline__ int region_of(const SNet& S, const int (&x)[NS]) {
+    int64_t d = 0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) d += (int64_t)S.rw[i] * (int64_t)x[i];
+    return d >= S.theta ? 1 : 0;
+}
+
+template <int NS>
+__device__ __forceinline__ int64_t hist_index(const SNet& S, const int (&x)[NS]) {
+    int64_t idx = 0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int64_t o = (int64_t)x[i] - S.hist_lo[i];
+        if (o < 0 || o >= S.hist_nb[i]) return -1;
+        idx += o * S.hist_stride[i];
+    }
+    return idx;
+}
+
+// FIM / RER integrands at x, times weight w, added through `add(slot, value)`
+// (Sec. III and Appendix A: FIM(x) = sum_j lam_j g_j g_j^T with
+// g_j = grad_c log lam_j; RER_k(x) = sum_j lam_j log(lam_j/lam'_j) - lam_j + lam'_j).
+template <int NS, class Add>
+__device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, Add add) {
+    const int np = S.np;
+    for (int j = 0; j < S.m; ++j) {
+        const double lam = prop_with<NS>(S, j, x, S.c);
+        if (!(lam > 0.0)) continue;
+        double g[kMaxP];
+#pragma unroll
+        for (int p = 0; p < kMaxP; ++p) g[p] = 0.0;
+        const int rp = S.rate_param[j];
+#pragma unroll
+        for (int p = 0; p < kMaxP; ++p)
+            if (p == rp) g[p] += 1.0 / S.c[rp];
+        for (int f = 0; f < S.nf[j]; ++f) {
+            if (S.fkind[j][f] != PARREP_HILL_REP) continue;
+            const double y = (double)pick<NS>(x, S.fsp[j][f]) / S.fK[j][f];
+            if (!(y > 0.0)) continue;
+            const int hp = S.fhp[j][f];
+            const double q = hill_pow(y, S.fhint[j][f], S.c[hp]);
+            const double d = -q * log(y) / (1.0 + q);
+#pragma unroll
+            for (int p = 0; p < kMaxP; ++p)
+                if (p == hp) g[p] += d;
+        }
+        for (int a = 0; a < np; ++a)
+            for (int bb = 0; bb < np; ++bb) add(kAccFim + a * np + bb, w * (lam * g[a] * g[bb]));
+    }
+    if (S.use_rer) {
+        for (int kp = 0; kp < np; ++kp) {
+            double cv[kMaxP];
+#pragma unroll
+            for (int p = 0; p < kMaxP; ++p) cv[p] = (p == kp) ? S.ceps[p] : S.c[p];
+            double h = 0.0;
+            for (int j = 0; j < S.m; ++j) {
+                const double lam = prop_with<NS>(S, j, x, S.c);
+                const double lp = prop_with<NS>(S, j, x, cv);
+                if (lam > 0.0) h += lam * log(lam / lp) - lam + lp;
+                else h += lp;
+            }
+            add(kAccRer + kp, w * h);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+        if (i < S.n) add(kAccY + i, w * (double)x[i]);
+}
+
+// Credit `full` time at x over [0,T] and `w` of it inside [t_burn, T].
+template <int NS>
+__device__ __forceinline__ void add_credit(const DevInst* I, const SNet& S, const int (&x)[NS],
+                                           double full, double w) {
+    const int64_t idx = hist_index<NS>(S, x);
+    if (idx >= 0) {
+        atomicAdd(&I->hist[idx], full);
+        if (w > 0.0) atomicAdd(&I->hist_w[idx], w);
+    } else {
+        atomicAdd(&I->acc[kAccOutside], full);
+        if (w > 0.0) {
+            atomicAdd(&I->acc[kAccOutsideW], w);
+            double* acc = I->acc;
+            fim_rer_point<NS>(S, x, w, [acc](int slot, double v) { atomicAdd(&acc[slot], v); });
+        }
+    }
+}
+
+// The generic crediting rule for one holding interval [C, C + tau) at x,
+// truncated at the horizon; returns true when the horizon is reached.
+template <int NS>
+__device__ __forceinline__ bool credit_event(const DevInst* I, const SNet& S, const int (&x)[NS],
+                                             double tau, Fx C, Fx Tq, Fx tbq, bool accum,
+                                             Fx& Cout) {
+    const Fx tq = fx_from(tau);
+    Fx E = fx_add(C, tq);
+    bool hit = false;
+    double full = tau;
+    if (fx_ge(E, Tq)) {
+        hit = true;
+        E = Tq;
+        full = fx_to_f64(fx_sub(E, C));
+    }
+    double w;
+    if (fx_ge(tbq, E)) w = 0.0;
+    else if (fx_ge(C, tbq)) w = full;
+    else w = fx_to_f64(fx_sub(E, tbq));
+    if (accum) add_credit<NS>(I, S, x, full, w);
+    Cout = E;
+    return hit;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup communication
+// ---------------------------------------------------------------------------
+template <int E, int WAVES>
+struct Shared {
+    int32_t flags[2][WAVES];
+    int32_t wmin[2][WAVES];
+    uint64_t wsum[2][WAVES][2];
+    uint64_t mask[E];
+    int32_t cnt[E];
+    int32_t pre[E];
+    int32_t nS;
+    int32_t bi[16];
+    uint64_t bu[8];
+};
+
+__device__ __forceinline__ Fx shfl_xor_fx(Fx v, int off) {
+    return Fx{__shfl_xor(v.hi, off), __shfl_xor(v.lo, off)};
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Position of the k-th (0-based) set bit of m.
+__device__ __forceinline__ int select_bit(uint64_t m, int k) {
+    int pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const uint64_t low = m & ((1ull << width) - 1ull);
+        const int c = __popcll(low);
+        if (k >= c) {
+            k -= c;
+            m >>= width;
+            pos += width;
+        }
+    }
+    return pos;
+}
+
+template <int E, int WAVES>
+__device__ __forceinline__ void block_min_sum(Shared<E, WAVES>& sh, int& par, int wid, int lane,
+                                              int vmin, Fx vsum, int& omin, Fx& osum) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        vmin = min(vmin, __shfl_xor(vmin, off));
+        vsum = fx_add(vsum, shfl_xor_fx(vsum, off));
+    }
+    if (WAVES == 1) {
+        omin = vmin;
+        osum = vsum;
+        return;
+    }
+    const int p = par;
+    par ^= 1;
+    if (lane == 0) {
+        sh.wmin[p][wid] = vmin;
+        sh.wsum[p][wid][0] = vsum.hi;
+        sh.wsum[p][wid][1] = vsum.lo;
+    }
+    __syncthreads();
+    omin = INT_MAX;
+    osum = Fx{0, 0};
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        omin = min(omin, sh.wmin[p][w]);
+        osum = fx_add(osum, Fx{sh.wsum[p][w][0], sh.wsum[p][w][1]});
+    }
+}
+
+template <int E, int WAVES>
+__device__ __forceinline__ int block_or_flags(Shared<E, WAVES>& sh, int& par, int wid, int lane,
+                                              int bits) {
+    const int any_exit = __ballot(bits & 1) != 0ull;
+    const int any_nd = __ballot(bits & 2) != 0ull;
+    const int f = any_exit | (any_nd << 1);
+    if (WAVES == 1) return f;
+    const int p = par;
+    par ^= 1;
+    if (lane == 0) sh.flags[p][wid] = f;
+    __syncthreads();
+    int o = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) o |= sh.flags[p][w];
+    return o;
+}
+
+template <int NS>
+__device__ void log_cycle(const DevInst* I, int64_t i, int64_t cyc, int64_t s1, int64_t s2,
+                          int64_t s3, int64_t K, int64_t phase, const int (&x)[NS]) {
+    if (!I->cycle_log || i >= I->cycle_log_cap) return;
+    int64_t* rec = I->cycle_log + i * PARREP_CYCLE_REC;
+    rec[0] = cyc;
+    rec[1] = s1;
+    rec[2] = s2;
+    rec[3] = s3;
+    rec[4] = K;
+    rec[5] = phase;
+    for (int k = 0; k < 4; ++k) rec[6 + k] = k < NS ? (int64_t)pick<NS>(x, k) : 0;
+    rec[10] = 0;
+    rec[11] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// The instance kernel
+// ---------------------------------------------------------------------------
+template <int NS, int RPL, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
+           int64_t hook_max_rounds) {
+    constexpr int B = 64 * WAVES;
+    constexpr int E = RPL * WAVES;
+    __shared__ SNet S;
+    __shared__ Shared<E, WAVES> sh;
+    extern __shared__ int32_t dyn_lds[];
+
+    const DevInst* I = insts + blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    if (tid == 0) load_net(S, I);
+    __syncthreads();
+
+    const int R = S.R;
+    const uint32_t key0 = I->seed, key1 = I->instance_id;
+    const bool accum = mode == kModeSolve;
+    // Fleming-Viot exchange: LDS when the shape's replica capacity fits 32 KiB
+    // (the launcher sizes dynamic LDS by the same rule), else global scratch.
+    constexpr bool kXbufLds = RPL * B * NS * 4 <= 32768;
+    int32_t* xbuf = kXbufLds ? dyn_lds : I->xbuf;
+    const int64_t max_ev = I->max_events > 0 ? I->max_events : (int64_t(1) << 50);
+    Fx Tq = fx_from(I->T), tbq = fx_from(I->t_burn);
+    if (mode == kModeParallelOnly) {
+        Tq = Fx{~0ull, ~0ull};
+        tbq = Tq;
+    }
+    int par = 0;
+
+    // Uniform run state (identical in every thread).
+    int xt[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) xt[i] = I->x0[i];
+    int W = region_of<NS>(S, xt);
+    uint32_t cycle = mode == kModeSolve ? 0u : hook_cycle;
+    Fx C{0, 0};
+    int64_t ev_total = 0;
+    int64_t c_decorr = 0, c_dephase = 0, c_cred = 0, c_disc = 0, c_cycles = 0, c_s3 = 0,
+            c_s2 = 0, c_fv = 0, n_log = 0;
+    int end_phase = 0;
+    int xend[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) xend[i] = xt[i];
+
+    int Y[RPL][NS];
+    double tr[RPL];
+    double tauk[RPL];
+    int Jk[RPL];
+
+    for (;;) {
+        // ------------------------------------------------------------------
+        // S1: decorrelation (serial; thread 0).  Every event is credited.
+        // ------------------------------------------------------------------
+        int64_t s1_events = 0;
+        if (mode == kModeSolve) {
+            if (tid == 0) {
+                const bool steps = I->decorr_mode == PARREP_STEPS;
+                const int64_t n_c = (int64_t)I->decorr;
+                const double t_c = I->decorr;
+                int64_t Nc = 0;
+                double e = 0.0;
+                int stop = 0;
+                for (;;) {
+                    if (steps ? (Nc >= n_c) : (e >= t_c)) break;
+                    if (ev_total + 1 > max_ev) {
+                        stop = 9;
+                        break;
+                    }
+                    const Blk b = draw((uint64_t)s1_events, 0u, cycle, kTagDecorr, key0, key1);
+                    double tau, a0;
+                    int J;
+                    ssa_event<NS>(S, xt, b, tau, J, a0);
+                    ++s1_events;
+                    ++ev_total;
+                    Fx Cn;
+                    if (credit_event<NS>(I, S, xt, tau, C, Tq, tbq, true, Cn)) {
+                        C = Cn;
+                        stop = 1;
+#pragma unroll
+                        for (int i = 0; i < NS; ++i) xend[i] = xt[i];
+                        break;
+                    }
+                    C = Cn;
+                    apply_jump<NS>(S, xt, J);
+                    const int rg = region_of<NS>(S, xt);
+                    if (rg == W) {
+                        Nc += 1;
+                        e = e + tau;
+                    } else {
+                        W = rg;
+                        Nc = 0;
+                        e = 0.0;
+                    }
+                }
+                if (stop == 9) {
+#pragma unroll
+                    for (int i = 0; i < NS; ++i) xend[i] = xt[i];
+                }
+                sh.bi[0] = stop;
+                sh.bi[1] = W;
+#pragma unroll
+                for (int i = 0; i < NS; ++i) {
+                    sh.bi[2 + i] = xt[i];
+                    sh.bi[6 + i] = xend[i];
+                }
+                sh.bu[0] = C.hi;
+                sh.bu[1] = C.lo;
+                sh.bu[2] = (uint64_t)ev_total;
+                sh.bu[3] = (uint64_t)s1_events;
+            }
+            __syncthreads();
+            const int stop = sh.bi[0];
+            W = sh.bi[1];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                xt[i] = sh.bi[2 + i];
+                xend[i] = sh.bi[6 + i];
+            }
+            C = Fx{sh.bu[0], sh.bu[1]};
+            ev_total = (int64_t)sh.bu[2];
+            s1_events = (int64_t)sh.bu[3];
+            c_decorr += s1_events;
+            __syncthreads();
+            if (stop) {
+                end_phase = stop;
+                if (tid == 0) log_cycle<NS>(I, n_log, cycle, s1_events, 0, 0, 0, stop, xend);
+                ++n_log;
+                break;
+            }
+        }
+
+        // ------------------------------------------------------------------
+        // S2: dephasing, Fleming-Viot restarts from uniformly chosen survivors.
+        // ------------------------------------------------------------------
+        int64_t round2 = 0;
+        bool budget = false;
+        if (mode != kModeParallelOnly) {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+#pragma unroll
+                for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
+                tr[k] = 0.0;
+            }
+            const bool steps = I->dephase_mode == PARREP_STEPS;
+            const int64_t n_p = (int64_t)I->dephase;
+            const double t_p = I->dephase;
+            bool done = steps ? (n_p <= 0) : (0.0 >= t_p);
+            while (!done) {
+                if (ev_total + R > max_ev) {
+                    budget = true;
+                    break;
+                }
+                ev_total += R;
+                c_dephase += R;
+                uint32_t exitbits = 0;
+                int bits = 0;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r < R) {
+                        const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagDephase, key0,
+                                           key1);
+                        double tau, a0;
+                        int J;
+                        ssa_event<NS>(S, Y[k], b, tau, J, a0);
+                        apply_jump<NS>(S, Y[k], J);
+                        tr[k] = tr[k] + tau;
+                        if (region_of<NS>(S, Y[k]) != W) {
+                            exitbits |= 1u << k;
+                            bits |= 1;
+                        }
+                        if (!(tr[k] >= t_p)) bits |= 2;
+                    }
+                }
+                const int fl = block_or_flags<E, WAVES>(sh, par, wid, lane, bits);
+                if (fl & 1) {
+                    // Survivors keep their post-round state; each exited
+                    // replica (ascending r) copies the post-round state of
+                    // survivor floor(u * |S|) in ascending order.
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = k * B + tid;
+                        if (r < R) {
+#pragma unroll
+                            for (int i = 0; i < NS; ++i) xbuf[r * NS + i] = Y[k][i];
+                        }
+                        const bool surv = (r < R) && !((exitbits >> k) & 1u);
+                        const uint64_t m = __ballot(surv);
+                        if (lane == 0) {
+                            sh.mask[k * WAVES + wid] = m;
+                            sh.cnt[k * WAVES + wid] = __popcll(m);
+                        }
+                    }
+                    __syncthreads();
+                    if (wid == 0) {
+                        int carry = 0;
+                        for (int base = 0; base < E; base += 64) {
+                            const int e = base + lane;
+                            const int v = e < E ? sh.cnt[e] : 0;
+                            const int inc = wave_incl_scan(v, lane);
+                            if (e < E) sh.pre[e] = carry + inc - v;
+                            carry += __shfl(inc, 63);
+                        }
+                        if (lane == 0) sh.nS = carry;
+                    }
+                    __syncthreads();
+                    const int nS = sh.nS;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        if (!((exitbits >> k) & 1u)) continue;
+                        const int r = k * B + tid;
+                        if (nS > 0) {
+                            const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagFV, key0,
+                                               key1);
+                            const int idx = (int)(((uint64_t)b.w0 * (uint64_t)nS) >> 32);
+                            int lo = 0, hi = E - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (sh.pre[mid] <= idx) lo = mid;
+                                else hi = mid - 1;
+                            }
+                            const int l = select_bit(sh.mask[lo], idx - sh.pre[lo]);
+                            const int rr = (lo / WAVES) * B + (lo % WAVES) * 64 + l;
+#pragma unroll
+                            for (int i = 0; i < NS; ++i) Y[k][i] = xbuf[rr * NS + i];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
+                        }
+                    }
+                    c_fv += R - nS;
+                    __syncthreads();
+                }
+                ++round2;
+                done = steps ? (round2 >= n_p) : !(fl & 2);
+            }
+            if (budget) {
+                end_phase = 9;
+#pragma unroll
+                for (int i = 0; i < NS; ++i) xend[i] = xt[i];
+                if (mode == kModeSolve && tid == 0)
+                    log_cycle<NS>(I, n_log, cycle, s1_events, 0, 0, 0, 9, xend);
+                ++n_log;
+                break;
+            }
+            c_s2 += round2;
+            if (mode == kModeDephaseOnly) {
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r < R) {
+#pragma unroll
+                        for (int i = 0; i < kMaxS; ++i)
+                            I->hook_states[r * kMaxS + i] = i < NS ? Y[k][i] : 0;
+                    }
+                }
+                if (tid == 0) I->hook_i64[0] = round2;
+                return;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int r = k * B + tid;
+#pragma unroll
+                for (int i = 0; i < NS; ++i) Y[k][i] = r < R ? I->hook_states[r * kMaxS + i] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < NS; ++i) xt[i] = I->hook_states[i];
+            W = region_of<NS>(S, xt);
+        }
+
+        // ------------------------------------------------------------------
+        // S3: parallel step.  Round n credits keys R(n-1)+r for r < K, the
+        // first replica outside W, at the pre-jump states (ParRep-CTMC rule).
+        // ------------------------------------------------------------------
+        int64_t round3 = 0;
+        bool hit = false, exited = false;
+        int Kx = 0;
+        for (;;) {
+            if ((mode == kModeParallelOnly && hook_max_rounds >= 0 && round3 >= hook_max_rounds) ||
+                ev_total + R > max_ev) {
+                budget = true;
+                break;
+            }
+            ev_total += R;
+            Fx lsum{0, 0};
+            int lfirst = INT_MAX;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int r = k * B + tid;
+                tauk[k] = 0.0;
+                Jk[k] = -1;
+                if (r < R) {
+                    const Blk b = draw((uint64_t)round3, (uint32_t)r, cycle, kTagParallel, key0,
+                                       key1);
+                    double a0;
+                    ssa_event<NS>(S, Y[k], b, tauk[k], Jk[k], a0);
+                    int post[NS];
+#pragma unroll
+                    for (int i = 0; i < NS; ++i) post[i] = Y[k][i];
+                    apply_jump<NS>(S, post, Jk[k]);
+                    if (region_of<NS>(S, post) != W && lfirst == INT_MAX) lfirst = r;
+                    lsum = fx_add(lsum, fx_from(tauk[k]));
+                }
+            }
+            int first;
+            Fx total;
+            block_min_sum<E, WAVES>(sh, par, wid, lane, lfirst, lsum, first, total);
+            ++round3;
+            const bool ex = first != INT_MAX;
+            const int K = ex ? first + 1 : R;
+            if (ex) {
+                Fx l2{0, 0};
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r < K) l2 = fx_add(l2, fx_from(tauk[k]));
+                }
+                int dummy;
+                block_min_sum<E, WAVES>(sh, par, wid, lane, INT_MAX, l2, dummy, total);
+            }
+            const Fx Cend = fx_add(C, total);
+            const bool boundary = fx_ge(Cend, Tq) || (fx_gt(tbq, C) && fx_gt(Cend, tbq));
+            int credited;
+            if (!boundary) {
+                if (accum) {
+                    const bool win = fx_ge(C, tbq);
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = k * B + tid;
+                        if (r < K) add_credit<NS>(I, S, Y[k], tauk[k], win ? tauk[k] : 0.0);
+                    }
+                }
+                C = Cend;
+                credited = K;
+            } else {
+                // Rare: an exact scan in key order finds where the burn-in
+                // time and the horizon fall.
+                uint64_t* sb = I->sbuf;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r < K) {
+                        const Fx tq = fx_from(tauk[k]);
+                        sb[4 * r] = tq.hi;
+                        sb[4 * r + 1] = tq.lo;
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    Fx s = C;
+                    int rend = K - 1, h = 0;
+                    for (int r = 0; r < K; ++r) {
+                        sb[4 * r + 2] = s.hi;
+                        sb[4 * r + 3] = s.lo;
+                        s = fx_add(s, Fx{sb[4 * r], sb[4 * r + 1]});
+                        if (fx_ge(s, Tq)) {
+                            rend = r;
+                            h = 1;
+                            s = Tq;
+                            break;
+                        }
+                    }
+                    sh.bi[0] = rend;
+                    sh.bi[1] = h;
+                    sh.bu[0] = s.hi;
+                    sh.bu[1] = s.lo;
+                }
+                __syncthreads();
+                const int rend = sh.bi[0];
+                hit = sh.bi[1] != 0;
+                const Fx Cn{sh.bu[0], sh.bu[1]};
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r <= rend) {
+                        const Fx st{sb[4 * r + 2], sb[4 * r + 3]};
+                        Fx dummy;
+                        credit_event<NS>(I, S, Y[k], tauk[k], st, Tq, tbq, accum, dummy);
+                        if (hit && r == rend) {
+#pragma unroll
+                            for (int i = 0; i < NS; ++i) sh.bi[2 + i] = Y[k][i];
+                        }
+                    }
+                }
+                C = Cn;
+                credited = rend + 1;
+                __syncthreads();
+                if (hit) {
+#pragma unroll
+                    for (int i = 0; i < NS; ++i) xend[i] = sh.bi[2 + i];
+                }
+                __syncthreads();
+            }
+            c_cred += credited;
+            if (hit || ex) c_disc += R - credited;
+            if (hit) break;
+            if (ex) {
+                // X~ <- post-jump state of replica K (1-based), then a new cycle.
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r == K - 1) {
+                        int post[NS];
+#pragma unroll
+                        for (int i = 0; i < NS; ++i) post[i] = Y[k][i];
+                        apply_jump<NS>(S, post, Jk[k]);
+#pragma unroll
+                        for (int i = 0; i < NS; ++i) sh.bi[2 + i] = post[i];
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < NS; ++i) xt[i] = sh.bi[2 + i];
+                __syncthreads();
+                exited = true;
+                Kx = K;
+                break;
+            }
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) apply_jump<NS>(S, Y[k], Jk[k]);
+        }
+        c_s3 += round3;
+        if (mode == kModeParallelOnly) {
+            if (tid == 0) {
+                I->hook_i64[0] = exited ? round3 : -1;
+                I->hook_i64[1] = exited ? Kx : 0;
+#pragma unroll
+                for (int i = 0; i < kMaxS; ++i) I->hook_exit[i] = i < NS ? xt[i] : 0;
+                I->hook_f64[0] = fx_to_f64(C);
+            }
+            return;
+        }
+        if (exited) {
+            if (tid == 0) log_cycle<NS>(I, n_log, cycle, s1_events, round2, round3, Kx, 3, xt);
+            ++n_log;
+            ++c_cycles;
+            W = region_of<NS>(S, xt);
+            ++cycle;
+            continue;
+        }
+        end_phase = hit ? 3 : 9;
+        if (!hit) {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) xend[i] = xt[i];
+        }
+        if (tid == 0) log_cycle<NS>(I, n_log, cycle, s1_events, round2, round3, 0, end_phase, xend);
+        ++n_log;
+        break;
+    }
+
+    if (mode == kModeDephaseOnly) {  // stopped by the event budget
+        if (tid == 0) I->hook_i64[0] = -1;
+        return;
+    }
+    if (tid == 0) {
+        int64_t* cn = I->counters;
+        cn[PARREP_CNT_EV_DECORR] = c_decorr;
+        cn[PARREP_CNT_EV_DEPHASE] = c_dephase;
+        cn[PARREP_CNT_EV_PAR_CREDITED] = c_cred;
+        cn[PARREP_CNT_EV_PAR_DISCARDED] = c_disc;
+        cn[PARREP_CNT_CYCLES] = c_cycles;
+        cn[PARREP_CNT_S3_ROUNDS] = c_s3;
+        cn[PARREP_CNT_S2_ROUNDS] = c_s2;
+        cn[PARREP_CNT_STATUS] = end_phase == 9 ? 1 : 0;
+        cn[PARREP_CNT_FV_RESTARTS] = c_fv;
+        cn[PARREP_CNT_END_PHASE] = end_phase;
+        cn[PARREP_CNT_N_CYCLE_LOG] = n_log;
+        cn[11] = 0;
+#pragma unroll
+        for (int i = 0; i < kMaxS; ++i) I->x_final[i] = i < NS ? xend[i] : 0;
+        I->stats[PARREP_ST_T] = fx_to_f64(C);
+    }
+}
+
+}  // namespace
+}  // namespace dev
+}  // namespace parrep

@@ -1,0 +1,46 @@
+// parrep_instance.hip -- explicit instantiations of the instance kernel for
+// one species count and one workgroup size (PARREP_NS species padded,
+// PARREP_WAVES 64-lane waves); compiled once per pair so the variants build
+// in parallel.
+#include "parrep_device.h"
+
+#ifndef PARREP_NS
+#error "PARREP_NS must be defined"
+#endif
+#ifndef PARREP_WAVES
+#error "PARREP_WAVES must be defined"
+#endif
+
+namespace parrep {
+namespace dev {
+namespace {
+
+template <int NS, int RPL, int WAVES>
+hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64_t hmr,
+                           int max_R, hipStream_t st) {
+    const size_t lds = (size_t)max_R * NS * 4 <= 32768 ? (size_t)max_R * NS * 4 : 0;
+    hipLaunchKernelGGL((k_instance<NS, RPL, WAVES>), dim3(n), dim3(64 * WAVES), lds, st, d, mode,
+                       hc, hmr);
+    return hipGetLastError();
+}
+
+
+}  // namespace
+}  // namespace dev
+
+#define PARREP_CAT2(a, b, c, d) a##b##c##d
+#define PARREP_CAT(a, b, c, d) PARREP_CAT2(a, b, c, d)
+#define PARREP_FN PARREP_CAT(launch_instance_ns, PARREP_NS, _w, PARREP_WAVES)
+
+hipError_t PARREP_FN(const DevInst* d, int n, int rpl, int mode, uint32_t hc, int64_t hmr,
+                     hipStream_t st) {
+    constexpr int NS = PARREP_NS, WV = PARREP_WAVES;
+    switch (rpl) {
+        case 1: return dev::launch_instance<NS, 1, WV>(d, n, mode, hc, hmr, 1 * 64 * WV, st);
+        case 4: return dev::launch_instance<NS, 4, WV>(d, n, mode, hc, hmr, 4 * 64 * WV, st);
+        case 16: return dev::launch_instance<NS, 16, WV>(d, n, mode, hc, hmr, 16 * 64 * WV, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace parrep

@@ -1,0 +1,93 @@
+// parrep_internal.h -- device-side descriptors shared by the kernels and the
+// C-ABI layer of libparrep (not installed; the public interface is parrep.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/parrep.h"
+
+namespace parrep {
+
+constexpr int kMaxS = PARREP_MAX_SPECIES;
+constexpr int kMaxM = PARREP_MAX_REACTIONS;
+constexpr int kMaxF = PARREP_MAX_FACTORS;
+constexpr int kMaxP = PARREP_MAX_PARAMS;
+
+// Philox counter word 3 carries the phase tag in its top nibble.
+enum : uint32_t { kTagDecorr = 1, kTagDephase = 2, kTagFV = 3, kTagParallel = 4 };
+
+struct DevFactor {
+    int32_t kind, species, order, hill_param;
+    double K;
+};
+
+struct DevReaction {
+    int32_t rate_param, n_factors;
+    double kappa;
+    int32_t stoich[kMaxS];
+    DevFactor f[kMaxF];
+};
+
+struct DevNet {
+    int32_t n_species, n_reactions, n_params, reserved;
+    DevReaction rx[kMaxM];
+};
+
+// Everything one ParRep instance needs on the device: the network, the
+// problem, its output buffers and its slice of the scratch arena.
+struct DevInst {
+    DevNet net;
+    double c[kMaxP], rer_eps[kMaxP];
+    int32_t use_rer, decorr_mode, dephase_mode, R;
+    double decorr, dephase, T, t_burn;
+    int32_t x0[kMaxS], region_w[kMaxS];
+    int64_t region_theta;
+    int32_t hist_lo[kMaxS], hist_nb[kMaxS];
+    int64_t hist_stride[kMaxS];
+    int64_t nbins;
+    uint32_t seed, instance_id;
+    int64_t max_events;
+    // outputs (caller-owned device memory)
+    double* hist;
+    double* hist_w;
+    double* stats;
+    int32_t* x_final;
+    int64_t* counters;
+    int64_t* cycle_log;
+    int32_t cycle_log_cap, reserved;
+    // library scratch
+    double* acc;         // kAccLen doubles: outside-box accumulators
+    int32_t* xbuf;       // R * kMaxS: Fleming-Viot state exchange
+    uint64_t* sbuf;      // R * 4: boundary-round clock scan (tau, start) as 64.64
+    // test-hook outputs (unused by full solves)
+    int32_t* hook_states;   // dephase-only: output states; parallel-only: input states
+    int32_t* hook_exit;     // parallel-only: exit state
+    int64_t* hook_i64;
+    double* hook_f64;
+};
+
+// acc[] layout: outside, outside_w, fim[kMaxP*kMaxP], rer[kMaxP], y[kMaxS]
+constexpr int kAccOutside = 0, kAccOutsideW = 1, kAccFim = 2, kAccRer = 2 + kMaxP * kMaxP,
+              kAccY = kAccRer + kMaxP, kAccLen = kAccY + kMaxS;
+
+// Run modes of the instance kernel.
+enum : int32_t { kModeSolve = 0, kModeDephaseOnly = 1, kModeParallelOnly = 2 };
+
+struct LaunchShape {
+    int rpl, waves, ns;
+};
+
+// Launchers (parrep_kernels.hip).
+hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, int mode,
+                        uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t stream);
+hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
+hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream);
+hipError_t launch_philox(int64_t n, const uint32_t* ctr_key, uint32_t* out, hipStream_t stream);
+hipError_t launch_events(const DevInst* d_inst, int64_t n, const int32_t* states,
+                         const uint32_t* blocks, double* a0, double* tau, int32_t* J,
+                         hipStream_t stream);
+bool shape_supported(LaunchShape s);
+LaunchShape choose_shape(int R, int ns);
+
+}  // namespace parrep

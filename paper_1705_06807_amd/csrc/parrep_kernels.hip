@@ -1,0 +1,168 @@
+// parrep_kernels.hip -- non-templated kernels of libparrep (accumulator
+// zeroing, FIM/RER finalize, test hooks) and the instance-kernel dispatch.
+#include "parrep_device.h"
+
+namespace parrep {
+namespace dev {
+
+// ---------------------------------------------------------------------------
+// Zero the accumulators of every instance.
+// ---------------------------------------------------------------------------
+__global__ void k_zero(const DevInst* __restrict__ insts) {
+    const DevInst* I = insts + blockIdx.y;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < I->nbins; i += stride) {
+        I->hist[i] = 0.0;
+        I->hist_w[i] = 0.0;
+    }
+    for (int64_t i = t0; i < kAccLen; i += stride) I->acc[i] = 0.0;
+    for (int64_t i = t0; i < PARREP_NSTATS; i += stride) I->stats[i] = 0.0;
+    for (int64_t i = t0; i < PARREP_NCOUNTERS; i += stride) I->counters[i] = 0;
+    if (I->cycle_log)
+        for (int64_t i = t0; i < (int64_t)I->cycle_log_cap * PARREP_CYCLE_REC; i += stride)
+            I->cycle_log[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: FIM, RER and window integrals from the window histogram
+// (the integrands depend on the state only, so int F(X_s) ds over the
+// window is sum_x hist_w(x) F(x)), plus the out-of-box accumulators.
+// ---------------------------------------------------------------------------
+template <int NS>
+__global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ insts) {
+    __shared__ SNet S;
+    __shared__ double acc[kAccLen];
+    const DevInst* I = insts + blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid == 0) load_net(S, I);
+    for (int i = tid; i < kAccLen; i += blockDim.x) acc[i] = 0.0;
+    __syncthreads();
+    for (int64_t idx = tid; idx < I->nbins; idx += blockDim.x) {
+        const double h = I->hist_w[idx];
+        if (h == 0.0) continue;
+        int x[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+            x[i] = S.hist_lo[i] + (int)((idx / S.hist_stride[i]) % S.hist_nb[i]);
+        fim_rer_point<NS>(S, x, h, [](int slot, double v) { atomicAdd(&acc[slot], v); });
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double win = I->T - I->t_burn;
+        const int np = S.np;
+        I->stats[PARREP_ST_OUTSIDE] = I->acc[kAccOutside];
+        I->stats[PARREP_ST_OUTSIDE_W] = I->acc[kAccOutsideW];
+        for (int a = 0; a < np * np; ++a)
+            I->stats[PARREP_ST_FIM + a] = (acc[kAccFim + a] + I->acc[kAccFim + a]) / win;
+        for (int a = 0; a < np; ++a)
+            I->stats[PARREP_ST_RER + a] = (acc[kAccRer + a] + I->acc[kAccRer + a]) / win;
+        for (int i = 0; i < S.n; ++i) I->stats[PARREP_ST_Y + i] = acc[kAccY + i] + I->acc[kAccY + i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Test hooks
+// ---------------------------------------------------------------------------
+__global__ void k_philox(int64_t n, const uint32_t* __restrict__ ck, uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t* q = ck + 6 * i;
+    const Blk b = philox10(q[0], q[1], q[2], q[3], q[4], q[5]);
+    out[4 * i] = b.w0;
+    out[4 * i + 1] = b.w1;
+    out[4 * i + 2] = b.w2;
+    out[4 * i + 3] = b.w3;
+}
+
+__global__ void k_events(const DevInst* __restrict__ inst, int64_t n,
+                         const int32_t* __restrict__ states, const uint32_t* __restrict__ blocks,
+                         double* a0o, double* tauo, int32_t* Jo) {
+    __shared__ SNet S;
+    if (threadIdx.x == 0) load_net(S, inst);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int x[kMaxS];
+#pragma unroll
+    for (int s = 0; s < kMaxS; ++s) x[s] = states[i * kMaxS + s];
+    const Blk b{blocks[4 * i], blocks[4 * i + 1], blocks[4 * i + 2], blocks[4 * i + 3]};
+    double tau, a0;
+    int J;
+    ssa_event<kMaxS>(S, x, b, tau, J, a0);
+    a0o[i] = a0;
+    tauo[i] = tau;
+    Jo[i] = J;
+}
+
+}  // namespace dev
+
+using namespace dev;
+
+bool shape_supported(LaunchShape s) {
+    const bool ns_ok = s.ns == 1 || s.ns == 2 || s.ns == 4;
+    const bool rpl_ok = s.rpl == 1 || s.rpl == 4 || s.rpl == 16;
+    const bool w_ok = s.waves == 1 || s.waves == 4 || s.waves == 16;
+    return ns_ok && rpl_ok && w_ok;
+}
+
+LaunchShape choose_shape(int R, int ns) {
+    const int nsv = ns <= 1 ? 1 : (ns <= 2 ? 2 : 4);
+    if (R <= 64) return {1, 1, nsv};
+    if (R <= 256) return {4, 1, nsv};
+    if (R <= 1024) return {16, 1, nsv};
+    if (R <= 4096) return {16, 4, nsv};
+    return {16, 16, nsv};
+}
+
+#define PARREP_DECL(NSv, Wv)                                                                  \
+    hipError_t launch_instance_ns##NSv##_w##Wv(const DevInst*, int, int, int, uint32_t, int64_t, \
+                                               hipStream_t);
+PARREP_DECL(1, 1) PARREP_DECL(1, 4) PARREP_DECL(1, 16)
+PARREP_DECL(2, 1) PARREP_DECL(2, 4) PARREP_DECL(2, 16)
+PARREP_DECL(4, 1) PARREP_DECL(4, 4) PARREP_DECL(4, 16)
+#undef PARREP_DECL
+
+hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mode,
+                        uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t stream) {
+    if (!shape_supported(s)) return hipErrorInvalidValue;
+#define PARREP_GO(NSv, Wv)                                                                    \
+    if (s.ns == NSv && s.waves == Wv)                                                         \
+        return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.rpl, mode, hook_cycle,       \
+                                               hook_max_rounds, stream);
+    PARREP_GO(1, 1) PARREP_GO(1, 4) PARREP_GO(1, 16)
+    PARREP_GO(2, 1) PARREP_GO(2, 4) PARREP_GO(2, 16)
+    PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
+#undef PARREP_GO
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero, dim3(64, n_inst), dim3(256), 0, stream, d_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream) {
+    // NS of the finalize kernel only sizes the state vector; 4 covers all.
+    hipLaunchKernelGGL((k_finalize<kMaxS>), dim3(n_inst), dim3(256), 0, stream, d_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(int64_t n, const uint32_t* ctr_key, uint32_t* out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)blocks), dim3(256), 0, stream, n, ctr_key, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_events(const DevInst* d_inst, int64_t n, const int32_t* states,
+                         const uint32_t* blocks, double* a0, double* tau, int32_t* J,
+                         hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_events, dim3((unsigned)nb), dim3(256), 0, stream, d_inst, n, states,
+                       blocks, a0, tau, J);
+    return hipGetLastError();
+}
+
+}  // namespace parrep

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same Philox streams.
+
+Integers (states, counters, cycle records, exit indices) must match exactly.
+Floats: the clock is an exact fixed-point sum on both sides, so T_s matches to
+the last bit up to the ulp-level difference between the device and host
+`log`; histograms, FIM, RER and window integrals differ only by summation
+order and must agree within 1e-12 relative (FIM/RER/Y are computed on the
+device from the window histogram, on the oracle per event; the two are equal
+in exact arithmetic).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1705_06807_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_06807_amd import binding
+    binding.lib()
+    return binding
+
+
+def _gpu_run(B, p, **kw):
+    import torch
+    out = B.parrep_solve(p, cycle_log_cap=kw.get("cycle_log_cap", 4096))
+    torch.cuda.synchronize()
+    return out.to_host()
+
+
+def assert_same(o, g, rtol=RTOL, what=""):
+    assert g.counters == o.counters, (what, g.counters, o.counters)
+    assert np.array_equal(g.x_final, o.x_final), (what, g.x_final, o.x_final)
+    assert np.array_equal(g.cycle_log, o.cycle_log), what
+    assert g.T_s == pytest.approx(o.T_s, rel=1e-15, abs=0), what
+    for name in ("hist", "hist_w"):
+        a, b = getattr(o, name), getattr(g, name)
+        scale = max(np.abs(a).max(), 1e-300)
+        err = np.abs(a - b).max() / scale
+        assert err < rtol, (what, name, err)
+        assert np.array_equal(a != 0, b != 0), (what, name, "support differs")
+    for name in ("outside", "outside_w"):
+        assert getattr(g, name) == pytest.approx(getattr(o, name), rel=rtol, abs=1e-300), what
+    for name in ("fim", "rer", "y"):
+        a, b = getattr(o, name), getattr(g, name)
+        scale = max(np.abs(a).max(), 1e-300)
+        assert np.abs(a - b).max() <= rtol * scale, (what, name, a, b)
+
+
+def test_philox_blocks(B, oracle):
+    rng = np.random.default_rng(0)
+    ck = rng.integers(0, 2 ** 32, size=(4096, 6), dtype=np.uint64).astype(np.uint32)
+    ck[:4] = [[0, 0, 0, 0, 0, 0], [0xFFFFFFFF] * 6, [1, 0, 0, 0, 0, 0], [0, 0, 5, 0, 0x1234, 0]]
+    got = B.parrep_philox(ck)
+    want = np.array([oracle.philox(c[:4], c[4:]) for c in ck])
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name", ["schlogl", "toggle", "toggle_beta"])
+def test_ssa_events(B, oracle, name):
+    rng = np.random.default_rng(1)
+    if name == "schlogl":
+        net, c = W.schlogl_classic(), W.SCHLOGL_CLASSIC_C
+        states = rng.integers(0, 1200, size=(3000, 1))
+        states[:4, 0] = [0, 1, 2, 3]
+    elif name == "toggle":
+        net, c = W.toggle(50.0), W.TOGGLE_C
+        states = rng.integers(0, 450, size=(3000, 2))
+        states[:3] = [[0, 0], [0, 9], [9, 0]]
+    else:  # non-integral Hill exponent: pow on both sides (tolerance path)
+        net, c = W.toggle(50.0), (3.0, 3.0, 2.5, 1.5)
+        states = rng.integers(0, 450, size=(3000, 2))
+    blocks = rng.integers(0, 2 ** 32, size=(len(states), 4), dtype=np.uint64).astype(np.uint32)
+    blocks[0] = [0xFFFFFFFF, 0xFFFFFFFF, 0, 0]
+    a0, tau, J = B.parrep_events(net, c, states, blocks)
+    for i in range(len(states)):
+        lam, oa0, otau, oJ, _ = oracle.event(net, c, states[i], blocks[i])
+        if name != "toggle_beta":
+            assert a0[i] == oa0, (i, a0[i], oa0)
+            assert J[i] == oJ, i
+        else:
+            assert a0[i] == pytest.approx(oa0, rel=1e-14)
+        assert tau[i] == pytest.approx(otau, rel=4e-16, abs=0), i
+
+
+C1_CASES = [
+    ("c1", lambda i: W.c1_schlogl(seed=0, instance_id=i)),
+    ("c1_R1", lambda i: W.c1_schlogl(seed=1, instance_id=i, R=1)),
+    ("c1_R100_ragged", lambda i: W.c1_schlogl(seed=2, instance_id=i, R=100)),
+    ("c1_steps", lambda i: W.c1_schlogl(seed=3, instance_id=i).replace(
+        decorr_mode=W.STEPS, decorr=400, dephase_mode=W.STEPS, dephase=300)),
+    ("c1_no_burn", lambda i: W.c1_schlogl(seed=4, instance_id=i).replace(t_burn=0.0)),
+    ("c1_budget", lambda i: W.c1_schlogl(seed=5, instance_id=i).replace(max_events=20000 + 997 * i)),
+    ("c1_narrow_hist", lambda i: W.c1_schlogl(seed=6, instance_id=i).replace(
+        hist_lo=(60,), hist_hi=(110,))),
+]
+
+
+@pytest.mark.parametrize("case", C1_CASES, ids=[c[0] for c in C1_CASES])
+def test_schlogl_solve_parity(B, oracle, case):
+    name, make = case
+    for i in range(3):
+        p = make(i)
+        _flush("case %s instance %d R=%d" % (name, i, p.R))
+        o = oracle.run(p, cycle_log_cap=4096)
+        g = _gpu_run(B, p)
+        assert_same(o, g, what="%s/%d" % (name, i))
+
+
+def _toggle_small(i, **kw):
+    # Omega = 5 switches every ~12 time units: many cycles, exits and FV restarts
+    p = W.c2_toggle(seed=11, instance_id=i, omega=5.0, R=kw.pop("R", 64), T=kw.pop("T", 300.0))
+    kw.setdefault("hist_hi", (40, 40))
+    return p.replace(**kw)
+
+
+TOGGLE_CASES = [
+    ("om5_R64", lambda i: _toggle_small(i)),
+    ("om5_R1000", lambda i: _toggle_small(i, R=1000, T=60.0)),
+    ("om5_R3000", lambda i: _toggle_small(i, R=3000, T=30.0)),
+    ("om5_R5000_global_fv", lambda i: _toggle_small(i, R=5000, T=20.0)),
+    ("om5_steps", lambda i: _toggle_small(i, decorr_mode=W.STEPS, decorr=50,
+                                          dephase_mode=W.STEPS, dephase=40)),
+    ("om5_outside_box", lambda i: _toggle_small(i, hist_lo=(2, 0), hist_hi=(12, 9))),
+    ("om50_R1024", lambda i: W.c2_toggle(seed=12, instance_id=i, T=20.0)),
+]
+
+
+@pytest.mark.parametrize("case", TOGGLE_CASES, ids=[c[0] for c in TOGGLE_CASES])
+def test_toggle_solve_parity(B, oracle, case):
+    name, make = case
+    for i in range(2):
+        p = make(i)
+        _flush("case %s instance %d R=%d" % (name, i, p.R))
+        o = oracle.run(p, cycle_log_cap=4096)
+        g = _gpu_run(B, p)
+        assert o.counters["n_cycle_log"] <= 4096
+        assert_same(o, g, what="%s/%d" % (name, i))
+
+
+def test_absorbing_state(B, oracle):
+    p = W.Problem(net=W.pure_death(), c=(1.0,), x0=(5,), region_w=(1,), region_theta=3, R=4,
+                  decorr_mode=W.STEPS, decorr=2, dephase_mode=W.STEPS, dephase=2, T=50.0,
+                  t_burn=25.0, hist_lo=(0,), hist_hi=(10,), rer_eps=None)
+    for i in range(8):
+        q = p.replace(instance_id=i)
+        assert_same(oracle.run(q, cycle_log_cap=4096), _gpu_run(B, q), what="absorbing")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (4, 1), (16, 1), (1, 4), (4, 4), (16, 4), (1, 16),
+                                   (4, 16)])
+def test_launch_shapes_agree(B, oracle, shape):
+    import torch
+    probs = [_toggle_small(i, R=60, T=100.0) for i in range(3)]
+    outs = B.parrep_solve_batch(probs, replicas_per_lane=shape[0], waves=shape[1],
+                                cycle_log_cap=4096)
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        assert_same(oracle.run(p, cycle_log_cap=4096), o.to_host(), what=str(shape))
+
+
+def test_mixed_batch_equals_oracle(B, oracle):
+    import torch
+    probs = W.c3_batch(seed=0, n_schlogl=6, n_toggle=6, r_lo=16, r_hi=700, T_schlogl=20.0,
+                       T_toggle=4.0)
+    outs = B.parrep_solve_batch(probs, cycle_log_cap=4096)
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        _flush("batch instance %d %s R=%d" % (p.instance_id, p.net.name, p.R))
+        assert_same(oracle.run(p, cycle_log_cap=4096), o.to_host(), what="batch")
+
+
+def test_dephase_hook(B, oracle):
+    for R, tp in ((64, 1.0), (1000, 0.5), (5000, 0.3)):
+        p = W.c2_toggle(seed=3, omega=5.0, R=R).replace(dephase=tp)
+        Yg, ng = B.parrep_dephase_only(p, (12, 3), cycle=7)
+        Yo, no = oracle.dephase(p, (12, 3), cycle=7)
+        assert ng == no and np.array_equal(Yg, Yo), R
+
+
+def test_parallel_hook(B, oracle):
+    rng = np.random.default_rng(5)
+    for R in (1, 16, 300):
+        for t in range(5):
+            p = W.c2_toggle(seed=9, instance_id=t, omega=2.0, R=R)
+            init = np.stack([rng.integers(3, 12, size=R), rng.integers(0, 3, size=R)], axis=1)
+            g = B.parrep_parallel_only(p, init, cycle=3)
+            o = oracle.parallel(p, init, cycle=3)
+            assert g[:2] == o[:2] and np.array_equal(g[2], o[2]), (R, t)
+            assert g[3] == pytest.approx(o[3], rel=1e-15)
+
+
+def test_full_size_toggle_sampled(B, oracle):
+    """Toggle Omega=50, R=1024, T=2e4 (the benchmark workload) in the launch
+    shape the benchmark uses; one sampled instance against the oracle, and
+    properties that hold for every instance."""
+    import torch
+    probs = [W.c2_toggle(seed=0, instance_id=i) for i in range(4)]
+    _flush("full-size toggle batch of %d" % len(probs))
+    outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+    torch.cuda.synchronize()
+    hs = [o.to_host() for o in outs]
+    for p, h in zip(probs, hs):
+        assert h.T_s == p.T
+        assert h.hist.sum() + h.outside == pytest.approx(p.T, rel=1e-12)
+        assert h.hist_w.sum() + h.outside_w == pytest.approx(p.T - p.t_burn, rel=1e-12)
+        assert h.counters["status"] == 0
+    if os.environ.get("PARREP_SKIP_SLOW_ORACLE") != "1":
+        _flush("oracle on instance 0 (about 30 s)")
+        o = oracle.run(probs[0], cycle_log_cap=0)
+        hs[0].cycle_log = None
+        o.cycle_log = None
+        assert_same(o, hs[0], what="full-size")
