@@ -77,7 +77,10 @@ enum {
     PARREP_CNT_STATUS = 7,           /* 0 horizon reached, 1 event budget hit, 2 aborted */
     PARREP_CNT_FV_RESTARTS = 8,
     PARREP_CNT_END_PHASE = 9,        /* 1 horizon in decorrelation, 3 in parallel step, 9 stopped */
-    PARREP_CNT_N_CYCLE_LOG = 10      /* cycle records produced (may exceed the capacity) */
+    PARREP_CNT_N_CYCLE_LOG = 10,     /* cycle records produced (may exceed the capacity) */
+    PARREP_CNT_SPILL_OVERFLOW = 11   /* credited events outside the histogram box whose state
+                                        found no spill slot (their time is in the outside
+                                        totals but not in FIM/RER/Y); 0 in normal runs */
 };
 
 /* stats[] layout of a result (PARREP_NSTATS doubles) */
@@ -167,8 +170,10 @@ const char* parrep_last_error(void);
 
 /* Define a reaction network (Sec. I A): n_species <= 4, n_reactions <= 8,
  * n_params <= 8, reactions rx[n_reactions] read during the call (host).
- * EINVAL when an index is out of range, an order exceeds 8, K <= 0 or kappa
- * is negative or not finite. */
+ * EINVAL when an index is out of range, an order exceeds 8, K <= 0, kappa
+ * is negative or not finite, or a stoichiometric coefficient is outside
+ * [-128, 127].  Solves need integral Hill exponents in [0, 64]
+ * (EUNSUPPORTED otherwise). */
 int parrep_net_create(parrep_ctx* ctx, int32_t n_species, int32_t n_reactions, int32_t n_params,
                       const parrep_reaction* rx, parrep_net** out);
 void parrep_net_destroy(parrep_net* net);

@@ -27,7 +27,7 @@ NSTATS = 80
 ST_T, ST_OUTSIDE, ST_OUTSIDE_W, ST_FIM, ST_RER, ST_Y = 0, 1, 2, 3, 67, 75
 COUNTER_NAMES = ("ev_decorr", "ev_dephase", "ev_par_credited", "ev_par_discarded", "cycles",
                  "s3_rounds", "s2_rounds", "status", "fv_restarts", "end_phase", "n_cycle_log",
-                 "reserved")
+                 "spill_overflow")
 
 
 class ParrepError(RuntimeError):

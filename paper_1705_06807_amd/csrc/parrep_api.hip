@@ -1,8 +1,10 @@
 // parrep_api.hip -- the C ABI of libparrep (declared in include/parrep.h):
 // argument validation, device descriptors, scratch, and kernel launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -49,8 +51,11 @@ int validate_problem(const parrep_net* net, const parrep_problem* p, int64_t* nb
     }
     for (int j = 0; j < N.n_reactions; ++j)
         for (int f = 0; f < N.rx[j].n_factors; ++f)
-            if (N.rx[j].f[f].kind == PARREP_HILL_REP && !(p->c[N.rx[j].f[f].hill_param] <= 64.0))
-                return fail(PARREP_EINVAL, "Hill exponents must be <= 64");
+            if (N.rx[j].f[f].kind == PARREP_HILL_REP) {
+                const double h = p->c[N.rx[j].f[f].hill_param];
+                if (!(h <= 64.0) || h != std::floor(h))
+                    return fail(PARREP_EUNSUPPORTED, "Hill exponents must be integers in [0, 64]");
+            }
     if (!(p->T > 0.0) || !(p->T < 0x1.0p51))
         return fail(PARREP_EINVAL, "T must be in (0, 2^51)");
     if (!(p->t_burn >= 0.0) || !(p->t_burn < p->T))
@@ -106,6 +111,25 @@ void fill_inst(DevInst& d, const parrep_net* net, const parrep_problem* p, int64
     d.seed = p->seed;
     d.instance_id = p->instance_id;
     d.max_events = p->max_events;
+    // Hot-path view: reactions with one state-dependent factor read a table
+    // of lambda_j over 0..tab_L-1 of that species.
+    for (int j = 0; j < kMaxM; ++j) {
+        const DevReaction& r = d.net.rx[j];
+        uint32_t kind = kRxConst, sp = 0;
+        if (j < d.net.n_reactions && r.n_factors == 1) {
+            kind = kRxTable;
+            sp = (uint32_t)r.f[0].species;
+        } else if (j < d.net.n_reactions && r.n_factors > 1) {
+            kind = kRxDirect;
+        }
+        d.jmeta[j] = kind | (sp << 2);
+        uint32_t packed = 0;
+        for (int i = 0; i < kMaxS; ++i) packed |= ((uint32_t)(r.stoich[i] & 0xFF)) << (8 * i);
+        d.jstoich[j] = packed;
+    }
+    int hi = 0;
+    for (int i = 0; i < n; ++i) hi = std::max(hi, std::max(p->hist_hi[i], p->x0[i]));
+    d.tab_L = std::min(8192, std::max(256, ((hi + 64 + 63) / 64) * 64));
 }
 
 // Device memory for one launch: descriptors plus per-instance scratch.
@@ -116,13 +140,38 @@ struct Arena {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Instances with the same network, rate vector and table length share one
+// propensity table; the first of them fills it.
+std::string table_key(const DevInst& d) {
+    std::string k(reinterpret_cast<const char*>(&d.net), sizeof(d.net));
+    k.append(reinterpret_cast<const char*>(d.c), sizeof(d.c));
+    k.append(reinterpret_cast<const char*>(&d.tab_L), sizeof(d.tab_L));
+    return k;
+}
+
 int alloc_arena(std::vector<DevInst>& insts, hipStream_t st, Arena& a, DevInst** d_insts) {
     const size_t n = insts.size();
     size_t off = align256(n * sizeof(DevInst));
-    std::vector<size_t> acc_off(n), x_off(n), s_off(n);
+    std::map<std::string, size_t> tables;
+    std::vector<size_t> tab_off(n);
+    for (size_t i = 0; i < n; ++i) {
+        auto it = tables.find(table_key(insts[i]));
+        if (it != tables.end()) {
+            tab_off[i] = it->second;
+            insts[i].tab_owner = 0;
+        } else {
+            tab_off[i] = off;
+            tables.emplace(table_key(insts[i]), off);
+            insts[i].tab_owner = 1;
+            off = align256(off + (size_t)kMaxM * insts[i].tab_L * sizeof(double));
+        }
+    }
+    std::vector<size_t> acc_off(n), x_off(n), s_off(n), sp_off(n);
     for (size_t i = 0; i < n; ++i) {
         acc_off[i] = off;
         off = align256(off + kAccLen * sizeof(double));
+        sp_off[i] = off;
+        off = align256(off + kSpillCap * sizeof(SpillSlot));
         x_off[i] = off;
         off = align256(off + (size_t)insts[i].R * kMaxS * sizeof(int32_t));
         s_off[i] = off;
@@ -133,7 +182,9 @@ int alloc_arena(std::vector<DevInst>& insts, hipStream_t st, Arena& a, DevInst**
     a.bytes = off;
     char* b = static_cast<char*>(a.base);
     for (size_t i = 0; i < n; ++i) {
+        insts[i].tab = reinterpret_cast<double*>(b + tab_off[i]);
         insts[i].acc = reinterpret_cast<double*>(b + acc_off[i]);
+        insts[i].spill = reinterpret_cast<SpillSlot*>(b + sp_off[i]);
         insts[i].xbuf = reinterpret_cast<int32_t*>(b + x_off[i]);
         insts[i].sbuf = reinterpret_cast<uint64_t*>(b + s_off[i]);
     }
@@ -163,8 +214,8 @@ int run_instances(parrep_ctx* ctx, std::vector<DevInst>& insts, LaunchShape shap
     rc = alloc_arena(insts, st, a, &d);
     if (rc) return rc;
     const int n = (int)insts.size();
-    hipError_t e = hipSuccess;
-    if (mode == kModeSolve) e = launch_zero(d, n, st);
+    hipError_t e = launch_setup(d, n, st);
+    if (e == hipSuccess && mode == kModeSolve) e = launch_zero(d, n, st);
     if (e == hipSuccess && ev_before) e = hipEventRecord(ev_before, st);
     if (e == hipSuccess) e = launch_solve(d, n, shape, mode, hook_cycle, hook_max_rounds, st);
     if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
@@ -240,7 +291,13 @@ int parrep_net_create(parrep_ctx* ctx, int32_t n_species, int32_t n_reactions, i
         d.rate_param = r.rate_param;
         d.n_factors = r.n_factors;
         d.kappa = r.kappa;
-        for (int i = 0; i < kMaxS; ++i) d.stoich[i] = i < n_species ? r.stoich[i] : 0;
+        for (int i = 0; i < kMaxS; ++i) {
+            d.stoich[i] = i < n_species ? r.stoich[i] : 0;
+            if (d.stoich[i] < -128 || d.stoich[i] > 127) {
+                delete net;
+                return fail(PARREP_EINVAL, "stoichiometric coefficients must be in [-128, 127]");
+            }
+        }
         for (int f = 0; f < r.n_factors; ++f) {
             const parrep_factor& q = r.factor[f];
             bool ok = q.species >= 0 && q.species < n_species;
@@ -335,6 +392,7 @@ int parrep_events(parrep_ctx* ctx, const parrep_net* net, const double* c_host, 
     if (rc) return rc;
     std::vector<DevInst> insts(1);
     fill_inst(insts[0], net, &p, nb);
+    insts[0].tab_L = 1024;  // states from 1024 on take the formula path
     rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -342,7 +400,8 @@ int parrep_events(parrep_ctx* ctx, const parrep_net* net, const double* c_host, 
     DevInst* d = nullptr;
     rc = alloc_arena(insts, st, a, &d);
     if (rc) return rc;
-    hipError_t e = launch_events(d, n, states, blocks, a0, tau, J, st);
+    hipError_t e = launch_setup(d, 1, st);
+    if (e == hipSuccess) e = launch_events(d, n, states, blocks, a0, tau, J, st);
     hipError_t ef = hipFreeAsync(a.base, st);
     if (e != hipSuccess) return hip_fail(e, "events launch");
     return ef == hipSuccess ? PARREP_OK : hip_fail(ef, "hipFreeAsync");

@@ -243,67 +243,198 @@ __device__ double prop_with(const SNet& S, int j, const int (&x)[NS], const doub
     return lam;
 }
 
-// One Gillespie event at x: holding time tau (+inf if absorbing) and channel J (-1).
+// ---------------------------------------------------------------------------
+// Hot-path propensities: uniform per-instance data is read from the
+// descriptor (scalar loads); per-lane work is table lookups.
+// ---------------------------------------------------------------------------
 template <int NS>
-__device__ __forceinline__ void ssa_event(const SNet& S, const int (&x)[NS], const Blk& b,
-                                          double& tau, int& J, double& a0) {
-    double cum[kMaxM];
-    double s = 0.0;
-    uint32_t pos = 0;
+__device__ __forceinline__ int xv(const int (&x)[NS], int i) {
+    return i < NS ? x[i] : 0;
+}
+
+// Add the packed stoichiometric change (int8 per species) to x.
+template <int NS>
+__device__ __forceinline__ void apply_dx(int (&x)[NS], uint32_t dxp) {
 #pragma unroll
-    for (int j = 0; j < kMaxM; ++j) {
-        cum[j] = 0.0;
-        if (j < S.m) {
-            double lam = S.k[j];
-            const int nf = S.nf[j];
-            for (int f = 0; f < nf; ++f) lam = lam * factor_val(S, j, f, pick<NS>(x, S.fsp[j][f]));
-            if (lam > 0.0) pos |= 1u << j;
-            s = s + lam;
-            cum[j] = s;
+    for (int i = 0; i < NS; ++i) x[i] += ((int32_t)(dxp << (24 - 8 * i))) >> 24;
+}
+
+// lambda_j(x) by its defining formula (states outside the tables and
+// two-factor reactions); exponents are the instance's integral Hill exponents.
+template <int NS>
+__device__ __forceinline__ double lambda_formula(const DevInst* __restrict__ I, int j,
+                                                 const int (&x)[NS]) {
+    double lam = I->k[j];
+    const int nf = I->net.rx[j].n_factors;
+    for (int f = 0; f < nf; ++f) {
+        const DevFactor& fc = I->net.rx[j].f[f];
+        const int xs = pick<NS>(x, fc.species);
+        double phi;
+        if (fc.kind == PARREP_FALLING) {
+            phi = falling(xs, fc.order);
+        } else {
+            const double y = (double)xs / fc.K;
+            const int h = I->hexp[j * kMaxF + f];
+            double q = 1.0;
+            if (h > 0) {
+                q = y;
+                for (int i = 1; i < h; ++i) q = q * y;
+            }
+            phi = 1.0 / (1.0 + q);
         }
+        lam = lam * phi;
     }
-    a0 = s;
+    return lam;
+}
+
+template <int NS>
+__device__ __forceinline__ double lam_j(const DevInst* __restrict__ I, int j, const int (&x)[NS]) {
+    const uint32_t meta = I->jmeta[j];
+    const uint32_t kind = meta & 3u;
+    if (kind == kRxConst) return I->k[j];
+    if (kind == kRxTable) {
+        const int xs = pick<NS>(x, (int)((meta >> 2) & 3u));
+        const int L = I->tab_L;
+        if ((unsigned)xs < (unsigned)L) return I->tab[j * L + xs];
+    }
+    return lambda_formula<NS>(I, j, x);
+}
+
+// One Gillespie event at x (the "generate tau and J" step of Alg. 1):
+// tau = -log(u_open)/a0 (+inf when absorbing) and the packed change of
+// channel J = first j with u_sel*a0 < S_j, S_j the left-to-right partial
+// sums (recomputed in a second pass; the same additions give the same sums).
+template <int NS>
+__device__ __forceinline__ void ssa_event(const DevInst* __restrict__ I, const int (&x)[NS],
+                                          const Blk& b, double& tau, int& J, uint32_t& dxp,
+                                          double* a0_out = nullptr) {
+    const int m = I->net.n_reactions;
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s = s + lam_j<NS>(I, j, x);
+    if (a0_out) *a0_out = s;
     if (!(s > 0.0)) {
         tau = __builtin_inf();
         J = -1;
+        dxp = 0;
         return;
     }
     tau = (-log(u_open(b))) / s;
     const double t = u_sel(b) * s;
-    int pj = -1;
-#pragma unroll
-    for (int j = kMaxM - 1; j >= 0; --j)
-        if (j < S.m && t < cum[j]) pj = j;
-    if (pj < 0) pj = 31 - __clz(pos);  // only for non-finite a0: last positive channel
+    double c = 0.0;
+    int pj = -1, last_pos = -1;
+    uint32_t d = 0;
+    for (int j = 0; j < m; ++j) {
+        const double l = lam_j<NS>(I, j, x);
+        c = c + l;
+        if (l > 0.0) last_pos = j;
+        if (pj < 0 && t < c) {
+            pj = j;
+            d = I->jstoich[j];
+        }
+    }
+    if (pj < 0) {  // only for non-finite a0: the last positive channel
+        pj = last_pos;
+        d = I->jstoich[pj];
+    }
     J = pj;
+    dxp = d;
 }
 
 template <int NS>
-__device__ __forceinline__ void apply_jump(const SNet& S, int (&x)[NS], int J) {
-    if (J < 0) return;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) x[i] += S.stoich[J][i];
-}
-
-template <int NS>
-__device__ __forceinline__ int region_of(const SNet& S, const int (&x)[NS]) {
+__device__ __forceinline__ int region_of(const DevInst* __restrict__ I, const int (&x)[NS]) {
     int64_t d = 0;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) d += (int64_t)S.rw[i] * (int64_t)x[i];
-    return d >= S.theta ? 1 : 0;
+    for (int i = 0; i < NS; ++i) d += (int64_t)I->region_w[i] * (int64_t)x[i];
+    return d >= I->region_theta ? 1 : 0;
 }
 
 template <int NS>
-__device__ __forceinline__ int64_t hist_index(const SNet& S, const int (&x)[NS]) {
+__device__ __forceinline__ int64_t hist_index(const DevInst* __restrict__ I, const int (&x)[NS]) {
     int64_t idx = 0;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-        const int64_t o = (int64_t)x[i] - S.hist_lo[i];
-        if (o < 0 || o >= S.hist_nb[i]) return -1;
-        idx += o * S.hist_stride[i];
+        const int64_t o = (int64_t)x[i] - I->hist_lo[i];
+        if (o < 0 || o >= I->hist_nb[i]) return -1;
+        idx += o * I->hist_stride[i];
     }
     return idx;
 }
+
+// Time at a state outside the histogram box: totals plus a slot of the
+// instance's spill table; counted in the overflow counter if no slot is free
+// (or a species is outside 0..32767).
+template <int NS>
+__device__ __forceinline__ void spill_credit(const DevInst* __restrict__ I, const int (&x)[NS], double full,
+                             double w) {
+    atomicAdd(&I->acc[kAccOutside], full);
+    if (w > 0.0) atomicAdd(&I->acc[kAccOutsideW], w);
+    unsigned long long key = 1ull << 63;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        ok = ok && x[i] >= 0 && x[i] <= 32767;
+        key |= (unsigned long long)(x[i] & 0x7FFF) << (15 * i);
+    }
+    if (ok) {
+        uint32_t h = (uint32_t)(key ^ (key >> 29)) * 0x9E3779B1u;
+        for (int probe = 0; probe < kSpillCap; ++probe) {
+            SpillSlot* sl = &I->spill[(h + probe) & (kSpillCap - 1)];
+            const unsigned long long old = atomicCAS(&sl->key, 0ull, key);
+            if (old == 0ull || old == key) {
+                atomicAdd(&sl->full, full);
+                if (w > 0.0) atomicAdd(&sl->w, w);
+                return;
+            }
+        }
+    }
+    atomicAdd((unsigned long long*)&I->counters[PARREP_CNT_SPILL_OVERFLOW], 1ull);
+}
+
+// Credit `full` time at x over [0,T] and `w` of it inside [t_burn, T].
+template <int NS>
+__device__ __forceinline__ void add_credit(const DevInst* __restrict__ I, const int (&x)[NS],
+                                           double full, double w) {
+    const int64_t idx = hist_index<NS>(I, x);
+    if (idx >= 0) {
+        atomicAdd(&I->hist[idx], full);
+        if (w > 0.0) atomicAdd(&I->hist_w[idx], w);
+    } else {
+        spill_credit<NS>(I, x, full, w);
+    }
+}
+
+// The generic crediting rule for one holding interval [C, C + tau) at x,
+// truncated at the horizon; returns true when the horizon is reached.
+template <int NS>
+__device__ __forceinline__ bool credit_event(const DevInst* __restrict__ I, const int (&x)[NS],
+                                             double tau, Fx C, Fx Tq, Fx tbq, bool accum,
+                                             Fx& Cout) {
+    const Fx tq = fx_from(tau);
+    Fx E = fx_add(C, tq);
+    bool hit = false;
+    double full = tau;
+    if (fx_ge(E, Tq)) {
+        hit = true;
+        E = Tq;
+        full = fx_to_f64(fx_sub(E, C));
+    }
+    double w;
+    if (fx_ge(tbq, E)) w = 0.0;
+    else if (fx_ge(C, tbq)) w = full;
+    else w = fx_to_f64(fx_sub(E, tbq));
+    if (accum) add_credit<NS>(I, x, full, w);
+    Cout = E;
+    return hit;
+}
+
+__device__ __forceinline__ uint32_t ufl(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ int ufl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t ufl64(uint64_t v) {
+    return ((uint64_t)ufl((uint32_t)(v >> 32)) << 32) | ufl((uint32_t)v);
+}
+__device__ __forceinline__ Fx ufx(Fx v) { return Fx{ufl64(v.hi), ufl64(v.lo)}; }
 
 // FIM / RER integrands at x, times weight w, added through `add(slot, value)`
 // (Sec. III and Appendix A: FIM(x) = sum_j lam_j g_j g_j^T with
@@ -353,48 +484,6 @@ __device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, Add a
 #pragma unroll
     for (int i = 0; i < NS; ++i)
         if (i < S.n) add(kAccY + i, w * (double)x[i]);
-}
-
-// Credit `full` time at x over [0,T] and `w` of it inside [t_burn, T].
-template <int NS>
-__device__ __forceinline__ void add_credit(const DevInst* I, const SNet& S, const int (&x)[NS],
-                                           double full, double w) {
-    const int64_t idx = hist_index<NS>(S, x);
-    if (idx >= 0) {
-        atomicAdd(&I->hist[idx], full);
-        if (w > 0.0) atomicAdd(&I->hist_w[idx], w);
-    } else {
-        atomicAdd(&I->acc[kAccOutside], full);
-        if (w > 0.0) {
-            atomicAdd(&I->acc[kAccOutsideW], w);
-            double* acc = I->acc;
-            fim_rer_point<NS>(S, x, w, [acc](int slot, double v) { atomicAdd(&acc[slot], v); });
-        }
-    }
-}
-
-// The generic crediting rule for one holding interval [C, C + tau) at x,
-// truncated at the horizon; returns true when the horizon is reached.
-template <int NS>
-__device__ __forceinline__ bool credit_event(const DevInst* I, const SNet& S, const int (&x)[NS],
-                                             double tau, Fx C, Fx Tq, Fx tbq, bool accum,
-                                             Fx& Cout) {
-    const Fx tq = fx_from(tau);
-    Fx E = fx_add(C, tq);
-    bool hit = false;
-    double full = tau;
-    if (fx_ge(E, Tq)) {
-        hit = true;
-        E = Tq;
-        full = fx_to_f64(fx_sub(E, C));
-    }
-    double w;
-    if (fx_ge(tbq, E)) w = 0.0;
-    else if (fx_ge(C, tbq)) w = full;
-    else w = fx_to_f64(fx_sub(E, tbq));
-    if (accum) add_credit<NS>(I, S, x, full, w);
-    Cout = E;
-    return hit;
 }
 
 // ---------------------------------------------------------------------------
@@ -506,7 +595,84 @@ __device__ void log_cycle(const DevInst* I, int64_t i, int64_t cyc, int64_t s1, 
 }
 
 // ---------------------------------------------------------------------------
-// The instance kernel
+// Per-instance run state that only changes between phases or rarely; kept in
+// LDS (written by thread 0, read after barriers) so that it does not occupy
+// vector registers in the replica loops.
+// ---------------------------------------------------------------------------
+struct RunState {
+    uint64_t C_hi, C_lo;
+    int64_t ev_total;
+    int64_t c_decorr, c_dephase, c_cred, c_disc, c_cycles, c_s3, c_s2, c_fv, n_log;
+    int64_t s1_events;
+    int32_t cycle, W, stop, end_phase;
+    int32_t xt[kMaxS], xend[kMaxS];
+};
+
+// S1, decorrelation (serial, thread 0): Alg. 1's loop over "generate tau and
+// J", credit, jump, count consecutive steps (or time) in the current set.
+template <int NS>
+__device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, RunState& rs, Fx Tq, Fx tbq,
+                            int64_t max_ev, uint32_t key0, uint32_t key1) {
+    const bool steps = I->decorr_mode == PARREP_STEPS;
+    const int64_t n_c = (int64_t)I->decorr;
+    const double t_c = I->decorr;
+    int x[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] = rs.xt[i];
+    int W = rs.W;
+    const uint32_t cycle = (uint32_t)rs.cycle;
+    Fx C{rs.C_hi, rs.C_lo};
+    int64_t ev = rs.ev_total;
+    int64_t Nc = 0, k = 0;
+    double e = 0.0;
+    int stop = 0;
+    for (;;) {
+        if (steps ? (Nc >= n_c) : (e >= t_c)) break;
+        if (ev + 1 > max_ev) {
+            stop = 9;
+            break;
+        }
+        const Blk b = draw((uint64_t)k, 0u, cycle, kTagDecorr, key0, key1);
+        double tau;
+        int J;
+        uint32_t dxp;
+        ssa_event<NS>(I, x, b, tau, J, dxp);
+        ++k;
+        ++ev;
+        Fx Cn;
+        const bool hit = credit_event<NS>(I, x, tau, C, Tq, tbq, true, Cn);
+        C = Cn;
+        if (hit) {
+            stop = 1;
+            break;
+        }
+        apply_dx<NS>(x, dxp);
+        const int rg = region_of<NS>(I, x);
+        if (rg == W) {
+            Nc += 1;
+            e = e + tau;
+        } else {
+            W = rg;
+            Nc = 0;
+            e = 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        rs.xt[i] = x[i];
+        if (stop) rs.xend[i] = x[i];
+    }
+    rs.W = W;
+    rs.C_hi = C.hi;
+    rs.C_lo = C.lo;
+    rs.ev_total = ev;
+    rs.c_decorr += k;
+    rs.s1_events = k;
+    rs.stop = stop;
+}
+
+// ---------------------------------------------------------------------------
+// The instance kernel: one workgroup runs Alg. 1 for one instance.
 // ---------------------------------------------------------------------------
 template <int NS, int RPL, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
@@ -514,18 +680,15 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
            int64_t hook_max_rounds) {
     constexpr int B = 64 * WAVES;
     constexpr int E = RPL * WAVES;
-    __shared__ SNet S;
+    __shared__ RunState rs;
     __shared__ Shared<E, WAVES> sh;
     extern __shared__ int32_t dyn_lds[];
 
-    const DevInst* I = insts + blockIdx.x;
+    const DevInst* __restrict__ I = insts + blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    if (tid == 0) load_net(S, I);
-    __syncthreads();
-
-    const int R = S.R;
+    const int R = I->R;
     const uint32_t key0 = I->seed, key1 = I->instance_id;
     const bool accum = mode == kModeSolve;
     // Fleming-Viot exchange: LDS when the shape's replica capacity fits 32 KiB
@@ -538,116 +701,59 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         Tq = Fx{~0ull, ~0ull};
         tbq = Tq;
     }
+    Tq = ufx(Tq);
+    tbq = ufx(tbq);
     int par = 0;
 
-    // Uniform run state (identical in every thread).
-    int xt[NS];
+    if (tid == 0) {
+        rs.C_hi = rs.C_lo = 0;
+        rs.ev_total = 0;
+        rs.c_decorr = rs.c_dephase = rs.c_cred = rs.c_disc = rs.c_cycles = 0;
+        rs.c_s3 = rs.c_s2 = rs.c_fv = rs.n_log = rs.s1_events = 0;
+        rs.cycle = mode == kModeSolve ? 0 : (int32_t)hook_cycle;
+        rs.stop = rs.end_phase = 0;
+        int x[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) xt[i] = I->x0[i];
-    int W = region_of<NS>(S, xt);
-    uint32_t cycle = mode == kModeSolve ? 0u : hook_cycle;
-    Fx C{0, 0};
-    int64_t ev_total = 0;
-    int64_t c_decorr = 0, c_dephase = 0, c_cred = 0, c_disc = 0, c_cycles = 0, c_s3 = 0,
-            c_s2 = 0, c_fv = 0, n_log = 0;
-    int end_phase = 0;
-    int xend[NS];
+        for (int i = 0; i < NS; ++i)
+            x[i] = mode == kModeParallelOnly ? I->hook_states[i] : I->x0[i];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) xend[i] = xt[i];
+        for (int i = 0; i < kMaxS; ++i) rs.xt[i] = rs.xend[i] = i < NS ? x[i] : 0;
+        rs.W = region_of<NS>(I, x);
+    }
+    __syncthreads();
 
     int Y[RPL][NS];
-    double tr[RPL];
-    double tauk[RPL];
-    int Jk[RPL];
-
     for (;;) {
         // ------------------------------------------------------------------
-        // S1: decorrelation (serial; thread 0).  Every event is credited.
+        // S1: decorrelation.
         // ------------------------------------------------------------------
-        int64_t s1_events = 0;
         if (mode == kModeSolve) {
-            if (tid == 0) {
-                const bool steps = I->decorr_mode == PARREP_STEPS;
-                const int64_t n_c = (int64_t)I->decorr;
-                const double t_c = I->decorr;
-                int64_t Nc = 0;
-                double e = 0.0;
-                int stop = 0;
-                for (;;) {
-                    if (steps ? (Nc >= n_c) : (e >= t_c)) break;
-                    if (ev_total + 1 > max_ev) {
-                        stop = 9;
-                        break;
-                    }
-                    const Blk b = draw((uint64_t)s1_events, 0u, cycle, kTagDecorr, key0, key1);
-                    double tau, a0;
-                    int J;
-                    ssa_event<NS>(S, xt, b, tau, J, a0);
-                    ++s1_events;
-                    ++ev_total;
-                    Fx Cn;
-                    if (credit_event<NS>(I, S, xt, tau, C, Tq, tbq, true, Cn)) {
-                        C = Cn;
-                        stop = 1;
-#pragma unroll
-                        for (int i = 0; i < NS; ++i) xend[i] = xt[i];
-                        break;
-                    }
-                    C = Cn;
-                    apply_jump<NS>(S, xt, J);
-                    const int rg = region_of<NS>(S, xt);
-                    if (rg == W) {
-                        Nc += 1;
-                        e = e + tau;
-                    } else {
-                        W = rg;
-                        Nc = 0;
-                        e = 0.0;
-                    }
-                }
-                if (stop == 9) {
-#pragma unroll
-                    for (int i = 0; i < NS; ++i) xend[i] = xt[i];
-                }
-                sh.bi[0] = stop;
-                sh.bi[1] = W;
-#pragma unroll
-                for (int i = 0; i < NS; ++i) {
-                    sh.bi[2 + i] = xt[i];
-                    sh.bi[6 + i] = xend[i];
-                }
-                sh.bu[0] = C.hi;
-                sh.bu[1] = C.lo;
-                sh.bu[2] = (uint64_t)ev_total;
-                sh.bu[3] = (uint64_t)s1_events;
-            }
+            if (tid == 0) decorrelate<NS>(I, rs, Tq, tbq, max_ev, key0, key1);
             __syncthreads();
-            const int stop = sh.bi[0];
-            W = sh.bi[1];
+            if (rs.stop) {
+                if (tid == 0) {
+                    rs.end_phase = rs.stop;
+                    int xe[NS];
 #pragma unroll
-            for (int i = 0; i < NS; ++i) {
-                xt[i] = sh.bi[2 + i];
-                xend[i] = sh.bi[6 + i];
-            }
-            C = Fx{sh.bu[0], sh.bu[1]};
-            ev_total = (int64_t)sh.bu[2];
-            s1_events = (int64_t)sh.bu[3];
-            c_decorr += s1_events;
-            __syncthreads();
-            if (stop) {
-                end_phase = stop;
-                if (tid == 0) log_cycle<NS>(I, n_log, cycle, s1_events, 0, 0, 0, stop, xend);
-                ++n_log;
+                    for (int i = 0; i < NS; ++i) xe[i] = rs.xend[i];
+                    log_cycle<NS>(I, rs.n_log, rs.cycle, rs.s1_events, 0, 0, 0, rs.stop, xe);
+                    rs.n_log += 1;
+                }
                 break;
             }
         }
+        const uint32_t cycle = ufl((uint32_t)rs.cycle);
+        const int W = ufl(rs.W);
+        int xt[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) xt[i] = ufl(rs.xt[i]);
 
         // ------------------------------------------------------------------
         // S2: dephasing, Fleming-Viot restarts from uniformly chosen survivors.
         // ------------------------------------------------------------------
         int64_t round2 = 0;
-        bool budget = false;
         if (mode != kModeParallelOnly) {
+            double tr[RPL];
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
 #pragma unroll
@@ -657,14 +763,16 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             const bool steps = I->dephase_mode == PARREP_STEPS;
             const int64_t n_p = (int64_t)I->dephase;
             const double t_p = I->dephase;
+            const int64_t left2 = (max_ev - rs.ev_total) / R;
+            const int64_t budget_rounds = (int64_t)ufl64((uint64_t)(left2 > 0 ? left2 : 0));
             bool done = steps ? (n_p <= 0) : (0.0 >= t_p);
+            bool budget = false;
+            int64_t fv = 0;
             while (!done) {
-                if (ev_total + R > max_ev) {
+                if (round2 >= budget_rounds) {
                     budget = true;
                     break;
                 }
-                ev_total += R;
-                c_dephase += R;
                 uint32_t exitbits = 0;
                 int bits = 0;
 #pragma unroll
@@ -673,12 +781,13 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     if (r < R) {
                         const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagDephase, key0,
                                            key1);
-                        double tau, a0;
+                        double tau;
                         int J;
-                        ssa_event<NS>(S, Y[k], b, tau, J, a0);
-                        apply_jump<NS>(S, Y[k], J);
+                        uint32_t dxp;
+                        ssa_event<NS>(I, Y[k], b, tau, J, dxp);
+                        apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
-                        if (region_of<NS>(S, Y[k]) != W) {
+                        if (region_of<NS>(I, Y[k]) != W) {
                             exitbits |= 1u << k;
                             bits |= 1;
                         }
@@ -688,8 +797,8 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 const int fl = block_or_flags<E, WAVES>(sh, par, wid, lane, bits);
                 if (fl & 1) {
                     // Survivors keep their post-round state; each exited
-                    // replica (ascending r) copies the post-round state of
-                    // survivor floor(u * |S|) in ascending order.
+                    // replica copies the post-round state of survivor
+                    // floor(u |S| / 2^32) in ascending replica order.
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         const int r = k * B + tid;
@@ -741,22 +850,30 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                             for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
                         }
                     }
-                    c_fv += R - nS;
+                    fv += R - nS;
                     __syncthreads();
                 }
                 ++round2;
                 done = steps ? (round2 >= n_p) : !(fl & 2);
             }
+            __syncthreads();
+            if (tid == 0) {
+                rs.ev_total += round2 * R;
+                rs.c_dephase += round2 * R;
+                rs.c_fv += fv;
+                if (!budget) rs.c_s2 += round2;
+            }
             if (budget) {
-                end_phase = 9;
+                if (tid == 0) {
+                    rs.end_phase = 9;
 #pragma unroll
-                for (int i = 0; i < NS; ++i) xend[i] = xt[i];
-                if (mode == kModeSolve && tid == 0)
-                    log_cycle<NS>(I, n_log, cycle, s1_events, 0, 0, 0, 9, xend);
-                ++n_log;
+                    for (int i = 0; i < NS; ++i) rs.xend[i] = xt[i];
+                    log_cycle<NS>(I, rs.n_log, cycle, rs.s1_events, 0, 0, 0, 9, xt);
+                    rs.n_log += 1;
+                }
+                if (mode == kModeDephaseOnly && tid == 0) I->hook_i64[0] = -1;
                 break;
             }
-            c_s2 += round2;
             if (mode == kModeDephaseOnly) {
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
@@ -777,48 +894,53 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
 #pragma unroll
                 for (int i = 0; i < NS; ++i) Y[k][i] = r < R ? I->hook_states[r * kMaxS + i] : 0;
             }
-#pragma unroll
-            for (int i = 0; i < NS; ++i) xt[i] = I->hook_states[i];
-            W = region_of<NS>(S, xt);
         }
+        __syncthreads();
 
         // ------------------------------------------------------------------
         // S3: parallel step.  Round n credits keys R(n-1)+r for r < K, the
         // first replica outside W, at the pre-jump states (ParRep-CTMC rule).
         // ------------------------------------------------------------------
-        int64_t round3 = 0;
-        bool hit = false, exited = false;
+        const int64_t left3 = (max_ev - rs.ev_total) / R;
+        int64_t budget3 = (int64_t)ufl64((uint64_t)(left3 > 0 ? left3 : 0));
+        if (mode == kModeParallelOnly && hook_max_rounds >= 0 && hook_max_rounds < budget3)
+            budget3 = hook_max_rounds;
+        Fx C = ufx(Fx{rs.C_hi, rs.C_lo});
+        int64_t round3 = 0, cred = 0, disc = 0;
+        int outcome = -1;  // 1 exit, 0 horizon, -1 budget
         int Kx = 0;
+        double tauk[RPL];
+        uint32_t dxk[RPL];
         for (;;) {
-            if ((mode == kModeParallelOnly && hook_max_rounds >= 0 && round3 >= hook_max_rounds) ||
-                ev_total + R > max_ev) {
-                budget = true;
+            if (round3 >= budget3) {
+                outcome = -1;
                 break;
             }
-            ev_total += R;
             Fx lsum{0, 0};
             int lfirst = INT_MAX;
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
                 const int r = k * B + tid;
                 tauk[k] = 0.0;
-                Jk[k] = -1;
+                dxk[k] = 0;
                 if (r < R) {
                     const Blk b = draw((uint64_t)round3, (uint32_t)r, cycle, kTagParallel, key0,
                                        key1);
-                    double a0;
-                    ssa_event<NS>(S, Y[k], b, tauk[k], Jk[k], a0);
+                    int J;
+                    ssa_event<NS>(I, Y[k], b, tauk[k], J, dxk[k]);
                     int post[NS];
 #pragma unroll
                     for (int i = 0; i < NS; ++i) post[i] = Y[k][i];
-                    apply_jump<NS>(S, post, Jk[k]);
-                    if (region_of<NS>(S, post) != W && lfirst == INT_MAX) lfirst = r;
+                    apply_dx<NS>(post, dxk[k]);
+                    if (region_of<NS>(I, post) != W && lfirst == INT_MAX) lfirst = r;
                     lsum = fx_add(lsum, fx_from(tauk[k]));
                 }
             }
             int first;
             Fx total;
             block_min_sum<E, WAVES>(sh, par, wid, lane, lfirst, lsum, first, total);
+            first = ufl(first);
+            total = ufx(total);
             ++round3;
             const bool ex = first != INT_MAX;
             const int K = ex ? first + 1 : R;
@@ -831,17 +953,19 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 }
                 int dummy;
                 block_min_sum<E, WAVES>(sh, par, wid, lane, INT_MAX, l2, dummy, total);
+                total = ufx(total);
             }
             const Fx Cend = fx_add(C, total);
             const bool boundary = fx_ge(Cend, Tq) || (fx_gt(tbq, C) && fx_gt(Cend, tbq));
             int credited;
+            bool hit = false;
             if (!boundary) {
                 if (accum) {
                     const bool win = fx_ge(C, tbq);
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         const int r = k * B + tid;
-                        if (r < K) add_credit<NS>(I, S, Y[k], tauk[k], win ? tauk[k] : 0.0);
+                        if (r < K) add_credit<NS>(I, Y[k], tauk[k], win ? tauk[k] : 0.0);
                     }
                 }
                 C = Cend;
@@ -880,9 +1004,9 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     sh.bu[1] = s.lo;
                 }
                 __syncthreads();
-                const int rend = sh.bi[0];
+                const int rend = ufl(sh.bi[0]);
                 hit = sh.bi[1] != 0;
-                const Fx Cn{sh.bu[0], sh.bu[1]};
+                const Fx Cn = ufx(Fx{sh.bu[0], sh.bu[1]});
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
@@ -890,25 +1014,23 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     if (r <= rend) {
                         const Fx st{sb[4 * r + 2], sb[4 * r + 3]};
                         Fx dummy;
-                        credit_event<NS>(I, S, Y[k], tauk[k], st, Tq, tbq, accum, dummy);
+                        credit_event<NS>(I, Y[k], tauk[k], st, Tq, tbq, accum, dummy);
                         if (hit && r == rend) {
 #pragma unroll
-                            for (int i = 0; i < NS; ++i) sh.bi[2 + i] = Y[k][i];
+                            for (int i = 0; i < NS; ++i) rs.xend[i] = Y[k][i];
                         }
                     }
                 }
                 C = Cn;
                 credited = rend + 1;
                 __syncthreads();
-                if (hit) {
-#pragma unroll
-                    for (int i = 0; i < NS; ++i) xend[i] = sh.bi[2 + i];
-                }
-                __syncthreads();
             }
-            c_cred += credited;
-            if (hit || ex) c_disc += R - credited;
-            if (hit) break;
+            cred += credited;
+            if (hit || ex) disc += R - credited;
+            if (hit) {
+                outcome = 0;
+                break;
+            }
             if (ex) {
                 // X~ <- post-jump state of replica K (1-based), then a new cycle.
 #pragma unroll
@@ -918,72 +1040,77 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         int post[NS];
 #pragma unroll
                         for (int i = 0; i < NS; ++i) post[i] = Y[k][i];
-                        apply_jump<NS>(S, post, Jk[k]);
+                        apply_dx<NS>(post, dxk[k]);
 #pragma unroll
-                        for (int i = 0; i < NS; ++i) sh.bi[2 + i] = post[i];
+                        for (int i = 0; i < NS; ++i) rs.xt[i] = post[i];
                     }
                 }
-                __syncthreads();
-#pragma unroll
-                for (int i = 0; i < NS; ++i) xt[i] = sh.bi[2 + i];
-                __syncthreads();
-                exited = true;
+                outcome = 1;
                 Kx = K;
                 break;
             }
 #pragma unroll
-            for (int k = 0; k < RPL; ++k) apply_jump<NS>(S, Y[k], Jk[k]);
+            for (int k = 0; k < RPL; ++k) apply_dx<NS>(Y[k], dxk[k]);
         }
-        c_s3 += round3;
+        __syncthreads();
         if (mode == kModeParallelOnly) {
             if (tid == 0) {
-                I->hook_i64[0] = exited ? round3 : -1;
-                I->hook_i64[1] = exited ? Kx : 0;
+                I->hook_i64[0] = outcome == 1 ? round3 : -1;
+                I->hook_i64[1] = outcome == 1 ? Kx : 0;
 #pragma unroll
-                for (int i = 0; i < kMaxS; ++i) I->hook_exit[i] = i < NS ? xt[i] : 0;
+                for (int i = 0; i < kMaxS; ++i) I->hook_exit[i] = i < NS ? rs.xt[i] : 0;
                 I->hook_f64[0] = fx_to_f64(C);
             }
             return;
         }
-        if (exited) {
-            if (tid == 0) log_cycle<NS>(I, n_log, cycle, s1_events, round2, round3, Kx, 3, xt);
-            ++n_log;
-            ++c_cycles;
-            W = region_of<NS>(S, xt);
-            ++cycle;
-            continue;
-        }
-        end_phase = hit ? 3 : 9;
-        if (!hit) {
+        if (tid == 0) {
+            rs.ev_total += round3 * R;
+            rs.c_cred += cred;
+            rs.c_disc += disc;
+            rs.c_s3 += round3;
+            rs.C_hi = C.hi;
+            rs.C_lo = C.lo;
+            int xl[NS];
+            if (outcome == 1) {
 #pragma unroll
-            for (int i = 0; i < NS; ++i) xend[i] = xt[i];
+                for (int i = 0; i < NS; ++i) xl[i] = rs.xt[i];
+                log_cycle<NS>(I, rs.n_log, cycle, rs.s1_events, round2, round3, Kx, 3, xl);
+                rs.c_cycles += 1;
+                rs.W = region_of<NS>(I, xl);
+                rs.cycle = (int32_t)(cycle + 1);
+            } else {
+                rs.end_phase = outcome == 0 ? 3 : 9;
+                if (outcome != 0) {
+#pragma unroll
+                    for (int i = 0; i < NS; ++i) rs.xend[i] = xt[i];
+                }
+#pragma unroll
+                for (int i = 0; i < NS; ++i) xl[i] = rs.xend[i];
+                log_cycle<NS>(I, rs.n_log, cycle, rs.s1_events, round2, round3, 0, rs.end_phase,
+                              xl);
+            }
+            rs.n_log += 1;
         }
-        if (tid == 0) log_cycle<NS>(I, n_log, cycle, s1_events, round2, round3, 0, end_phase, xend);
-        ++n_log;
-        break;
+        __syncthreads();
+        if (outcome != 1) break;
     }
 
-    if (mode == kModeDephaseOnly) {  // stopped by the event budget
-        if (tid == 0) I->hook_i64[0] = -1;
-        return;
-    }
     if (tid == 0) {
         int64_t* cn = I->counters;
-        cn[PARREP_CNT_EV_DECORR] = c_decorr;
-        cn[PARREP_CNT_EV_DEPHASE] = c_dephase;
-        cn[PARREP_CNT_EV_PAR_CREDITED] = c_cred;
-        cn[PARREP_CNT_EV_PAR_DISCARDED] = c_disc;
-        cn[PARREP_CNT_CYCLES] = c_cycles;
-        cn[PARREP_CNT_S3_ROUNDS] = c_s3;
-        cn[PARREP_CNT_S2_ROUNDS] = c_s2;
-        cn[PARREP_CNT_STATUS] = end_phase == 9 ? 1 : 0;
-        cn[PARREP_CNT_FV_RESTARTS] = c_fv;
-        cn[PARREP_CNT_END_PHASE] = end_phase;
-        cn[PARREP_CNT_N_CYCLE_LOG] = n_log;
-        cn[11] = 0;
+        cn[PARREP_CNT_EV_DECORR] = rs.c_decorr;
+        cn[PARREP_CNT_EV_DEPHASE] = rs.c_dephase;
+        cn[PARREP_CNT_EV_PAR_CREDITED] = rs.c_cred;
+        cn[PARREP_CNT_EV_PAR_DISCARDED] = rs.c_disc;
+        cn[PARREP_CNT_CYCLES] = rs.c_cycles;
+        cn[PARREP_CNT_S3_ROUNDS] = rs.c_s3;
+        cn[PARREP_CNT_S2_ROUNDS] = rs.c_s2;
+        cn[PARREP_CNT_STATUS] = rs.end_phase == 9 ? 1 : 0;
+        cn[PARREP_CNT_FV_RESTARTS] = rs.c_fv;
+        cn[PARREP_CNT_END_PHASE] = rs.end_phase;
+        cn[PARREP_CNT_N_CYCLE_LOG] = rs.n_log;
 #pragma unroll
-        for (int i = 0; i < kMaxS; ++i) I->x_final[i] = i < NS ? xend[i] : 0;
-        I->stats[PARREP_ST_T] = fx_to_f64(C);
+        for (int i = 0; i < kMaxS; ++i) I->x_final[i] = i < NS ? rs.xend[i] : 0;
+        I->stats[PARREP_ST_T] = fx_to_f64(Fx{rs.C_hi, rs.C_lo});
     }
 }
 

@@ -36,6 +36,16 @@ struct DevNet {
 
 // Everything one ParRep instance needs on the device: the network, the
 // problem, its output buffers and its slice of the scratch arena.
+// Time spent at states outside the histogram box, keyed by the packed state
+// (15 bits per species, bit 63 marks a used slot); the finalize kernel adds
+// their FIM, RER and window-integral contributions.
+struct SpillSlot {
+    unsigned long long key;
+    double full;
+    double w;
+};
+constexpr int kSpillCap = 2048;
+
 struct DevInst {
     DevNet net;
     double c[kMaxP], rer_eps[kMaxP];
@@ -56,8 +66,18 @@ struct DevInst {
     int64_t* counters;
     int64_t* cycle_log;
     int32_t cycle_log_cap, reserved;
+    // hot-path network view (jmeta/jstoich/tab_L filled on the host from the
+    // network; k and the tables computed on the device by the setup kernel)
+    double k[kMaxM];          // k_j = c[rate_param] * kappa (kappa when rate_param < 0)
+    uint32_t jmeta[kMaxM];    // bits 0-1 kind (0 constant, 1 table, 2 direct), 2-3 species
+    uint32_t jstoich[kMaxM];  // eta_j packed as int8 per species (species i in bits 8i..8i+7)
+    int32_t hexp[kMaxM * kMaxF];  // integral Hill exponents (setup kernel)
+    int32_t tab_L;            // table entries per reaction (states 0..tab_L-1)
+    int32_t tab_owner;        // 1: this instance's setup block fills the table
+    double* tab;              // kMaxM * tab_L propensities, shared by equal (network, c)
     // library scratch
     double* acc;         // kAccLen doubles: outside-box accumulators
+    SpillSlot* spill;    // kSpillCap slots: time at states outside the histogram box
     int32_t* xbuf;       // R * kMaxS: Fleming-Viot state exchange
     uint64_t* sbuf;      // R * 4: boundary-round clock scan (tau, start) as 64.64
     // test-hook outputs (unused by full solves)
@@ -74,6 +94,9 @@ constexpr int kAccOutside = 0, kAccOutsideW = 1, kAccFim = 2, kAccRer = 2 + kMax
 // Run modes of the instance kernel.
 enum : int32_t { kModeSolve = 0, kModeDephaseOnly = 1, kModeParallelOnly = 2 };
 
+// Hot-path reaction kinds (DevInst::jmeta bits 0-1).
+enum : uint32_t { kRxConst = 0, kRxTable = 1, kRxDirect = 2 };
+
 struct LaunchShape {
     int rpl, waves, ns;
 };
@@ -82,6 +105,7 @@ struct LaunchShape {
 hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, int mode,
                         uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t stream);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
+hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_philox(int64_t n, const uint32_t* ctr_key, uint32_t* out, hipStream_t stream);
 hipError_t launch_events(const DevInst* d_inst, int64_t n, const int32_t* states,

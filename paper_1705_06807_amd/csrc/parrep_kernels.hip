@@ -6,6 +6,37 @@ namespace parrep {
 namespace dev {
 
 // ---------------------------------------------------------------------------
+// Setup: rate constants k_j = c[rate_param] * kappa of every instance, and the
+// propensity tables lambda_j(x_s), x_s = 0..tab_L-1, of each reaction whose
+// propensity depends on one species (computed by the defining formula, so a
+// table entry is bit-identical to evaluating the formula at that state).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_setup(DevInst* __restrict__ insts) {
+    __shared__ SNet S;
+    DevInst* I = insts + blockIdx.x;
+    if (threadIdx.x == 0) {
+        load_net(S, I);
+        for (int j = 0; j < kMaxM; ++j) {
+            I->k[j] = S.k[j];
+            for (int f = 0; f < kMaxF; ++f) I->hexp[j * kMaxF + f] = S.fhint[j][f];
+        }
+    }
+    __syncthreads();
+    if (!I->tab_owner) return;
+    const int L = I->tab_L;
+    const int m = S.m;
+    for (int idx = threadIdx.x; idx < m * L; idx += blockDim.x) {
+        const int j = idx / L;
+        const int xs = idx - j * L;
+        const uint32_t meta = I->jmeta[j];
+        if ((meta & 3u) != kRxTable) continue;
+        int x[kMaxS] = {0, 0, 0, 0};
+        x[(meta >> 2) & 3u] = xs;
+        I->tab[idx] = prop_with<kMaxS>(S, j, x, S.c);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Zero the accumulators of every instance.
 // ---------------------------------------------------------------------------
 __global__ void k_zero(const DevInst* __restrict__ insts) {
@@ -17,6 +48,11 @@ __global__ void k_zero(const DevInst* __restrict__ insts) {
         I->hist_w[i] = 0.0;
     }
     for (int64_t i = t0; i < kAccLen; i += stride) I->acc[i] = 0.0;
+    for (int64_t i = t0; i < kSpillCap; i += stride) {
+        I->spill[i].key = 0;
+        I->spill[i].full = 0.0;
+        I->spill[i].w = 0.0;
+    }
     for (int64_t i = t0; i < PARREP_NSTATS; i += stride) I->stats[i] = 0.0;
     for (int64_t i = t0; i < PARREP_NCOUNTERS; i += stride) I->counters[i] = 0;
     if (I->cycle_log)
@@ -47,17 +83,24 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
             x[i] = S.hist_lo[i] + (int)((idx / S.hist_stride[i]) % S.hist_nb[i]);
         fim_rer_point<NS>(S, x, h, [](int slot, double v) { atomicAdd(&acc[slot], v); });
     }
+    // states outside the box: their window time sits in the spill table
+    for (int i = tid; i < kSpillCap; i += blockDim.x) {
+        const SpillSlot sl = I->spill[i];
+        if (sl.key == 0ull || !(sl.w > 0.0)) continue;
+        int x[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x[s] = (int)((sl.key >> (15 * s)) & 0x7FFF);
+        fim_rer_point<NS>(S, x, sl.w, [](int slot, double v) { atomicAdd(&acc[slot], v); });
+    }
     __syncthreads();
     if (tid == 0) {
         const double win = I->T - I->t_burn;
         const int np = S.np;
         I->stats[PARREP_ST_OUTSIDE] = I->acc[kAccOutside];
         I->stats[PARREP_ST_OUTSIDE_W] = I->acc[kAccOutsideW];
-        for (int a = 0; a < np * np; ++a)
-            I->stats[PARREP_ST_FIM + a] = (acc[kAccFim + a] + I->acc[kAccFim + a]) / win;
-        for (int a = 0; a < np; ++a)
-            I->stats[PARREP_ST_RER + a] = (acc[kAccRer + a] + I->acc[kAccRer + a]) / win;
-        for (int i = 0; i < S.n; ++i) I->stats[PARREP_ST_Y + i] = acc[kAccY + i] + I->acc[kAccY + i];
+        for (int a = 0; a < np * np; ++a) I->stats[PARREP_ST_FIM + a] = acc[kAccFim + a] / win;
+        for (int a = 0; a < np; ++a) I->stats[PARREP_ST_RER + a] = acc[kAccRer + a] / win;
+        for (int i = 0; i < S.n; ++i) I->stats[PARREP_ST_Y + i] = acc[kAccY + i];
     }
 }
 
@@ -89,7 +132,8 @@ __global__ void k_events(const DevInst* __restrict__ inst, int64_t n,
     const Blk b{blocks[4 * i], blocks[4 * i + 1], blocks[4 * i + 2], blocks[4 * i + 3]};
     double tau, a0;
     int J;
-    ssa_event<kMaxS>(S, x, b, tau, J, a0);
+    uint32_t dxp;
+    ssa_event<kMaxS>(inst, x, b, tau, J, dxp, &a0);
     a0o[i] = a0;
     tauo[i] = tau;
     Jo[i] = J;
@@ -135,6 +179,11 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mo
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
 #undef PARREP_GO
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream) {
+    hipLaunchKernelGGL(k_setup, dim3(n_inst), dim3(256), 0, stream, d_inst);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream) {
