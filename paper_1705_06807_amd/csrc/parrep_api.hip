@@ -214,10 +214,14 @@ int run_instances(parrep_ctx* ctx, std::vector<DevInst>& insts, LaunchShape shap
     rc = alloc_arena(insts, st, a, &d);
     if (rc) return rc;
     const int n = (int)insts.size();
+    int max_tab = 0;
+    for (const DevInst& di : insts) max_tab = std::max(max_tab, di.net.n_reactions * di.tab_L);
+    const int tab_lds = table_lds_doubles(shape, max_tab);
     hipError_t e = launch_setup(d, n, st);
     if (e == hipSuccess && mode == kModeSolve) e = launch_zero(d, n, st);
     if (e == hipSuccess && ev_before) e = hipEventRecord(ev_before, st);
-    if (e == hipSuccess) e = launch_solve(d, n, shape, mode, hook_cycle, hook_max_rounds, st);
+    if (e == hipSuccess)
+        e = launch_solve(d, n, shape, mode, hook_cycle, hook_max_rounds, tab_lds, st);
     if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
     if (e == hipSuccess && mode == kModeSolve) e = launch_finalize(d, n, st);
     hipError_t ef = hipFreeAsync(a.base, st);

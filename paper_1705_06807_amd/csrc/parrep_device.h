@@ -287,15 +287,18 @@ __device__ __forceinline__ double lambda_formula(const DevInst* __restrict__ I, 
     return lam;
 }
 
+// lambda_j(x): constant, table entry (the LDS copy when the workgroup holds
+// one, else the global table), or the defining formula.
 template <int NS>
-__device__ __forceinline__ double lam_j(const DevInst* __restrict__ I, int j, const int (&x)[NS]) {
+__device__ __forceinline__ double lam_j(const DevInst* __restrict__ I, const double* ltab, int j,
+                                        const int (&x)[NS]) {
     const uint32_t meta = I->jmeta[j];
     const uint32_t kind = meta & 3u;
     if (kind == kRxConst) return I->k[j];
     if (kind == kRxTable) {
         const int xs = pick<NS>(x, (int)((meta >> 2) & 3u));
         const int L = I->tab_L;
-        if ((unsigned)xs < (unsigned)L) return I->tab[j * L + xs];
+        if ((unsigned)xs < (unsigned)L) return ltab ? ltab[j * L + xs] : I->tab[j * L + xs];
     }
     return lambda_formula<NS>(I, j, x);
 }
@@ -305,12 +308,12 @@ __device__ __forceinline__ double lam_j(const DevInst* __restrict__ I, int j, co
 // channel J = first j with u_sel*a0 < S_j, S_j the left-to-right partial
 // sums (recomputed in a second pass; the same additions give the same sums).
 template <int NS>
-__device__ __forceinline__ void ssa_event(const DevInst* __restrict__ I, const int (&x)[NS],
-                                          const Blk& b, double& tau, int& J, uint32_t& dxp,
-                                          double* a0_out = nullptr) {
+__device__ __forceinline__ void ssa_event(const DevInst* __restrict__ I, const double* ltab,
+                                          const int (&x)[NS], const Blk& b, double& tau, int& J,
+                                          uint32_t& dxp, double* a0_out = nullptr) {
     const int m = I->net.n_reactions;
     double s = 0.0;
-    for (int j = 0; j < m; ++j) s = s + lam_j<NS>(I, j, x);
+    for (int j = 0; j < m; ++j) s = s + lam_j<NS>(I, ltab, j, x);
     if (a0_out) *a0_out = s;
     if (!(s > 0.0)) {
         tau = __builtin_inf();
@@ -324,7 +327,7 @@ __device__ __forceinline__ void ssa_event(const DevInst* __restrict__ I, const i
     int pj = -1, last_pos = -1;
     uint32_t d = 0;
     for (int j = 0; j < m; ++j) {
-        const double l = lam_j<NS>(I, j, x);
+        const double l = lam_j<NS>(I, ltab, j, x);
         c = c + l;
         if (l > 0.0) last_pos = j;
         if (pj < 0 && t < c) {
@@ -496,8 +499,6 @@ struct Shared {
     uint64_t wsum[2][WAVES][2];
     uint64_t mask[E];
     int32_t cnt[E];
-    int32_t pre[E];
-    int32_t nS;
     int32_t bi[16];
     uint64_t bu[8];
 };
@@ -611,8 +612,9 @@ struct RunState {
 // S1, decorrelation (serial, thread 0): Alg. 1's loop over "generate tau and
 // J", credit, jump, count consecutive steps (or time) in the current set.
 template <int NS>
-__device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, RunState& rs, Fx Tq, Fx tbq,
-                            int64_t max_ev, uint32_t key0, uint32_t key1) {
+__device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, const double* ltab,
+                                            RunState& rs, Fx Tq, Fx tbq, int64_t max_ev,
+                                            uint32_t key0, uint32_t key1) {
     const bool steps = I->decorr_mode == PARREP_STEPS;
     const int64_t n_c = (int64_t)I->decorr;
     const double t_c = I->decorr;
@@ -636,7 +638,7 @@ __device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, RunSt
         double tau;
         int J;
         uint32_t dxp;
-        ssa_event<NS>(I, x, b, tau, J, dxp);
+        ssa_event<NS>(I, ltab, x, b, tau, J, dxp);
         ++k;
         ++ev;
         Fx Cn;
@@ -674,10 +676,17 @@ __device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, RunSt
 // ---------------------------------------------------------------------------
 // The instance kernel: one workgroup runs Alg. 1 for one instance.
 // ---------------------------------------------------------------------------
+// Occupancy target per shape: with 4 replicas per lane the allocator is
+// asked to fit 4 waves per SIMD (at most 128 VGPRs); other shapes fit their
+// natural size.
+template <int RPL>
+constexpr int kMinWavesPerEU = RPL == 4 ? 4 : 1;
+
 template <int NS, int RPL, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL>, 8)))
 k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
-           int64_t hook_max_rounds) {
+           int64_t hook_max_rounds, int tab_lds_doubles) {
     constexpr int B = 64 * WAVES;
     constexpr int E = RPL * WAVES;
     __shared__ RunState rs;
@@ -694,7 +703,16 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
     // Fleming-Viot exchange: LDS when the shape's replica capacity fits 32 KiB
     // (the launcher sizes dynamic LDS by the same rule), else global scratch.
     constexpr bool kXbufLds = RPL * B * NS * 4 <= 32768;
+    constexpr int kXbufInts = kXbufLds ? RPL * B * NS : 0;
     int32_t* xbuf = kXbufLds ? dyn_lds : I->xbuf;
+    // Propensity tables: copied into LDS (after the exchange buffer) when the
+    // launch reserved room for them (tab_lds_doubles > 0), else read from HBM.
+    double* ltab = nullptr;
+    if (tab_lds_doubles > 0) {
+        ltab = reinterpret_cast<double*>(dyn_lds + ((kXbufInts + 1) & ~1));
+        const int nt = I->net.n_reactions * I->tab_L;
+        for (int i = tid; i < nt; i += B) ltab[i] = I->tab[i];
+    }
     const int64_t max_ev = I->max_events > 0 ? I->max_events : (int64_t(1) << 50);
     Fx Tq = fx_from(I->T), tbq = fx_from(I->t_burn);
     if (mode == kModeParallelOnly) {
@@ -728,7 +746,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         // S1: decorrelation.
         // ------------------------------------------------------------------
         if (mode == kModeSolve) {
-            if (tid == 0) decorrelate<NS>(I, rs, Tq, tbq, max_ev, key0, key1);
+            if (tid == 0) decorrelate<NS>(I, ltab, rs, Tq, tbq, max_ev, key0, key1);
             __syncthreads();
             if (rs.stop) {
                 if (tid == 0) {
@@ -784,7 +802,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         double tau;
                         int J;
                         uint32_t dxp;
-                        ssa_event<NS>(I, Y[k], b, tau, J, dxp);
+                        ssa_event<NS>(I, ltab, Y[k], b, tau, J, dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
                         if (region_of<NS>(I, Y[k]) != W) {
@@ -798,7 +816,9 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 if (fl & 1) {
                     // Survivors keep their post-round state; each exited
                     // replica copies the post-round state of survivor
-                    // floor(u |S| / 2^32) in ascending replica order.
+                    // floor(u |S| / 2^32) in ascending replica order.  The
+                    // next round's flag exchange orders these reads before
+                    // the exchange buffer is written again.
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         const int r = k * B + tid;
@@ -814,44 +834,37 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         }
                     }
                     __syncthreads();
-                    if (wid == 0) {
-                        int carry = 0;
-                        for (int base = 0; base < E; base += 64) {
-                            const int e = base + lane;
-                            const int v = e < E ? sh.cnt[e] : 0;
-                            const int inc = wave_incl_scan(v, lane);
-                            if (e < E) sh.pre[e] = carry + inc - v;
-                            carry += __shfl(inc, 63);
-                        }
-                        if (lane == 0) sh.nS = carry;
-                    }
-                    __syncthreads();
-                    const int nS = sh.nS;
+                    int nS = 0;
+                    for (int e = 0; e < E; ++e) nS += sh.cnt[e];
+                    nS = ufl(nS);
+                    if (exitbits) {
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        if (!((exitbits >> k) & 1u)) continue;
-                        const int r = k * B + tid;
-                        if (nS > 0) {
-                            const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagFV, key0,
-                                               key1);
-                            const int idx = (int)(((uint64_t)b.w0 * (uint64_t)nS) >> 32);
-                            int lo = 0, hi = E - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (sh.pre[mid] <= idx) lo = mid;
-                                else hi = mid - 1;
+                        for (int k = 0; k < RPL; ++k) {
+                            if (!((exitbits >> k) & 1u)) continue;
+                            const int r = k * B + tid;
+                            if (nS > 0) {
+                                const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagFV,
+                                                   key0, key1);
+                                int idx = (int)(((uint64_t)b.w0 * (uint64_t)nS) >> 32);
+                                int e = 0;
+                                for (;;) {
+                                    const int c = sh.cnt[e];
+                                    if (idx < c) break;
+                                    idx -= c;
+                                    ++e;
+                                }
+                                const int l = select_bit(sh.mask[e], idx);
+                                const int rr = (e / WAVES) * B + (e % WAVES) * 64 + l;
+#pragma unroll
+                                for (int i = 0; i < NS; ++i) Y[k][i] = xbuf[rr * NS + i];
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
                             }
-                            const int l = select_bit(sh.mask[lo], idx - sh.pre[lo]);
-                            const int rr = (lo / WAVES) * B + (lo % WAVES) * 64 + l;
-#pragma unroll
-                            for (int i = 0; i < NS; ++i) Y[k][i] = xbuf[rr * NS + i];
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
                         }
                     }
                     fv += R - nS;
-                    __syncthreads();
+                    if (WAVES == 1) __syncthreads();
                 }
                 ++round2;
                 done = steps ? (round2 >= n_p) : !(fl & 2);
@@ -927,7 +940,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     const Blk b = draw((uint64_t)round3, (uint32_t)r, cycle, kTagParallel, key0,
                                        key1);
                     int J;
-                    ssa_event<NS>(I, Y[k], b, tauk[k], J, dxk[k]);
+                    ssa_event<NS>(I, ltab, Y[k], b, tauk[k], J, dxk[k]);
                     int post[NS];
 #pragma unroll
                     for (int i = 0; i < NS; ++i) post[i] = Y[k][i];

@@ -15,12 +15,17 @@ namespace parrep {
 namespace dev {
 namespace {
 
+// Dynamic LDS: the Fleming-Viot exchange buffer when the shape's replica
+// capacity fits 32 KiB (the kernel applies the same rule), then, if
+// tab_doubles > 0, the propensity tables.
 template <int NS, int RPL, int WAVES>
 hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64_t hmr,
-                           int max_R, hipStream_t st) {
-    const size_t lds = (size_t)max_R * NS * 4 <= 32768 ? (size_t)max_R * NS * 4 : 0;
+                           int tab_doubles, hipStream_t st) {
+    constexpr size_t xints = (size_t)RPL * 64 * WAVES * NS;
+    const size_t xb = xints * 4 <= 32768 ? ((xints + 1) & ~size_t(1)) * 4 : 0;
+    const size_t lds = xb + (size_t)tab_doubles * 8;
     hipLaunchKernelGGL((k_instance<NS, RPL, WAVES>), dim3(n), dim3(64 * WAVES), lds, st, d, mode,
-                       hc, hmr);
+                       hc, hmr, tab_doubles);
     return hipGetLastError();
 }
 
@@ -33,12 +38,12 @@ hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64
 #define PARREP_FN PARREP_CAT(launch_instance_ns, PARREP_NS, _w, PARREP_WAVES)
 
 hipError_t PARREP_FN(const DevInst* d, int n, int rpl, int mode, uint32_t hc, int64_t hmr,
-                     hipStream_t st) {
+                     int tab_doubles, hipStream_t st) {
     constexpr int NS = PARREP_NS, WV = PARREP_WAVES;
     switch (rpl) {
-        case 1: return dev::launch_instance<NS, 1, WV>(d, n, mode, hc, hmr, 1 * 64 * WV, st);
-        case 4: return dev::launch_instance<NS, 4, WV>(d, n, mode, hc, hmr, 4 * 64 * WV, st);
-        case 16: return dev::launch_instance<NS, 16, WV>(d, n, mode, hc, hmr, 16 * 64 * WV, st);
+        case 1: return dev::launch_instance<NS, 1, WV>(d, n, mode, hc, hmr, tab_doubles, st);
+        case 4: return dev::launch_instance<NS, 4, WV>(d, n, mode, hc, hmr, tab_doubles, st);
+        case 16: return dev::launch_instance<NS, 16, WV>(d, n, mode, hc, hmr, tab_doubles, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -103,7 +103,11 @@ struct LaunchShape {
 
 // Launchers (parrep_kernels.hip).
 hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, int mode,
-                        uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t stream);
+                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_lds_doubles,
+                        hipStream_t stream);
+// Doubles of propensity table to stage in LDS per workgroup for this shape
+// (0: read the tables from HBM).
+int table_lds_doubles(LaunchShape shape, int max_table_doubles);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream);

@@ -133,7 +133,7 @@ __global__ void k_events(const DevInst* __restrict__ inst, int64_t n,
     double tau, a0;
     int J;
     uint32_t dxp;
-    ssa_event<kMaxS>(inst, x, b, tau, J, dxp, &a0);
+    ssa_event<kMaxS>(inst, nullptr, x, b, tau, J, dxp, &a0);
     a0o[i] = a0;
     tauo[i] = tau;
     Jo[i] = J;
@@ -154,26 +154,27 @@ LaunchShape choose_shape(int R, int ns) {
     const int nsv = ns <= 1 ? 1 : (ns <= 2 ? 2 : 4);
     if (R <= 64) return {1, 1, nsv};
     if (R <= 256) return {4, 1, nsv};
-    if (R <= 1024) return {16, 1, nsv};
-    if (R <= 4096) return {16, 4, nsv};
+    if (R <= 1024) return {4, 4, nsv};
+    if (R <= 4096) return {4, 16, nsv};
     return {16, 16, nsv};
 }
 
 #define PARREP_DECL(NSv, Wv)                                                                  \
     hipError_t launch_instance_ns##NSv##_w##Wv(const DevInst*, int, int, int, uint32_t, int64_t, \
-                                               hipStream_t);
+                                               int, hipStream_t);
 PARREP_DECL(1, 1) PARREP_DECL(1, 4) PARREP_DECL(1, 16)
 PARREP_DECL(2, 1) PARREP_DECL(2, 4) PARREP_DECL(2, 16)
 PARREP_DECL(4, 1) PARREP_DECL(4, 4) PARREP_DECL(4, 16)
 #undef PARREP_DECL
 
 hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mode,
-                        uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t stream) {
+                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_lds_doubles,
+                        hipStream_t stream) {
     if (!shape_supported(s)) return hipErrorInvalidValue;
 #define PARREP_GO(NSv, Wv)                                                                    \
     if (s.ns == NSv && s.waves == Wv)                                                         \
         return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.rpl, mode, hook_cycle,       \
-                                               hook_max_rounds, stream);
+                                               hook_max_rounds, tab_lds_doubles, stream);
     PARREP_GO(1, 1) PARREP_GO(1, 4) PARREP_GO(1, 16)
     PARREP_GO(2, 1) PARREP_GO(2, 4) PARREP_GO(2, 16)
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
@@ -184,6 +185,14 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mo
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream) {
     hipLaunchKernelGGL(k_setup, dim3(n_inst), dim3(256), 0, stream, d_inst);
     return hipGetLastError();
+}
+
+int table_lds_doubles(LaunchShape s, int max_table_doubles) {
+    const size_t xints = (size_t)s.rpl * 64 * s.waves * s.ns;
+    const size_t xb = xints * 4 <= 32768 ? xints * 4 : 0;
+    const size_t budget = 56 * 1024;  // leaves room for the static LDS of the kernel
+    if (xb + (size_t)max_table_doubles * 8 > budget) return 0;
+    return max_table_doubles;
 }
 
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream) {
