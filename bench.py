@@ -25,9 +25,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSA events/s on 1 GPU (% VALU peak); batched/served ParRep solves/s + p50/p99"
 
-# VALU issue model of one toggle-switch SSA event (derived in the design doc):
-# lane-op slots per event at CDNA issue cost.
-VALU_SLOTS_PER_EVENT = 238
+# Algorithmic VALU work of one SSA event of the toggle switch, in wave64
+# issue slots per lane-event (CDNA issue cost: a full-rate op 1 slot, a
+# quarter-rate op such as the 32x32->64 multiply 4 slots): Philox4x32-10
+# 20 multiplies + 40 XOR = 120; two uniforms 15; four table propensities and
+# their partial sums 12; tau = -log(u)/a0 33; selection 13; jump 4; set test
+# 3; time-mode clock 2.  Total 202 (derivation in the design doc).
+VALU_SLOTS_PER_EVENT = 202
 # MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz, a wave64 VALU op takes 4 cycles
 # -> 256*4*16*2.4e9 = 3.93e13 lane-op slots per second.
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
@@ -68,7 +72,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=512,
+    ap.add_argument("--instances", type=int, default=4096,
                     help="independent trajectories per step")
     ap.add_argument("--T", type=float, default=2e4)
     ap.add_argument("--rpl", type=int, default=0, help="replicas per lane (0 = library choice)")
@@ -76,6 +80,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-T", type=float, default=1000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phase-clock", action="store_true",
+                    help="report where each trajectory's workgroup spent its time")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -94,7 +100,7 @@ def main():
     B.lib()
     ctx = B.context(0)
     probs = [W.c2_toggle(seed=0, instance_id=i, T=args.T) for i in range(args.instances)]
-    outs = [B.Outputs(ctx, p, cycle_log_cap=0) for p in probs]
+    outs = [B.Outputs(ctx, p, cycle_log_cap=0, phase_clock=args.phase_clock) for p in probs]
     ev_b = torch.cuda.Event(enable_timing=True)
     ev_a = torch.cuda.Event(enable_timing=True)
     ev_b.record()
@@ -170,6 +176,14 @@ def main():
             "ops_per_event": VALU_SLOTS_PER_EVENT,
         },
     }
+    if args.phase_clock:
+        hz = B.lib().parrep_wall_clock_hz(ctx.h)
+        pc = torch.stack([o.phase_clock for o in outs]).cpu().double() / hz
+        tot = pc[:, 3]
+        line["phase_seconds_per_trajectory"] = {
+            "decorrelation": pc[:, 0].mean().item(), "dephasing": pc[:, 1].mean().item(),
+            "parallel": pc[:, 2].mean().item(), "total_mean": tot.mean().item(),
+            "total_max": tot.max().item(), "total_min": tot.min().item()}
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log("cpu baseline: %d threads, ~%.0f s" % (threads, args.cpu_seconds))

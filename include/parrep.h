@@ -147,6 +147,10 @@ typedef struct {
                               end phase, state after the cycle[4], 0, 0}               */
     int32_t cycle_log_cap;
     int32_t reserved;
+    int64_t* phase_clock; /* device, 4 int64 or NULL: wall-clock ticks the workgroup spent in
+                             decorrelation, dephasing, the parallel step, and in total
+                             (ticks of the device's constant wall clock, see
+                             parrep_wall_clock_hz)                                       */
 } parrep_result;
 
 /* Launch shape for the batched solve: replicas per lane and waves per
@@ -164,6 +168,9 @@ typedef struct {
  * compiled kernels.  EDEVICE if the device cannot be used. */
 int parrep_ctx_create(int device, parrep_ctx** out);
 void parrep_ctx_destroy(parrep_ctx* ctx);
+
+/* Frequency in Hz of the wall clock that phase_clock counts (0 on error). */
+double parrep_wall_clock_hz(parrep_ctx* ctx);
 
 /* Thread-local message for the last failing call of this thread. */
 const char* parrep_last_error(void);

@@ -58,7 +58,8 @@ class Problem(C.Structure):
 class Result(C.Structure):
     _fields_ = [("hist", C.c_void_p), ("hist_window", C.c_void_p), ("stats", C.c_void_p),
                 ("x_final", C.c_void_p), ("counters", C.c_void_p), ("cycle_log", C.c_void_p),
-                ("cycle_log_cap", C.c_int32), ("reserved", C.c_int32)]
+                ("cycle_log_cap", C.c_int32), ("reserved", C.c_int32),
+                ("phase_clock", C.c_void_p)]
 
 
 class Launch(C.Structure):
@@ -80,6 +81,8 @@ def lib():
             L = C.CDLL(LIB_PATH)
             vp = C.c_void_p
             L.parrep_last_error.restype = C.c_char_p
+            L.parrep_wall_clock_hz.argtypes = [vp]
+            L.parrep_wall_clock_hz.restype = C.c_double
             L.parrep_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
             L.parrep_ctx_destroy.argtypes = [vp]
             L.parrep_net_create.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32,
@@ -191,7 +194,8 @@ def problem_struct(p: W.Problem) -> Problem:
 class Outputs:
     """Device output buffers of one solve (torch tensors)."""
 
-    def __init__(self, ctx: Context, p: W.Problem, cycle_log_cap: int = 256):
+    def __init__(self, ctx: Context, p: W.Problem, cycle_log_cap: int = 256,
+                 phase_clock: bool = False):
         torch = _torch()
         dev = ctx.torch_device
         self.problem = p
@@ -204,6 +208,8 @@ class Outputs:
         self.cycle_log_cap = cycle_log_cap
         self.cycle_log = torch.empty((max(cycle_log_cap, 1), CYCLE_REC), dtype=torch.int64,
                                      device=dev)
+        self.phase_clock = (torch.zeros(4, dtype=torch.int64, device=dev) if phase_clock
+                            else None)
 
     def struct(self) -> Result:
         r = Result()
@@ -214,6 +220,7 @@ class Outputs:
         r.counters = self.counters.data_ptr()
         r.cycle_log = self.cycle_log.data_ptr() if self.cycle_log_cap > 0 else None
         r.cycle_log_cap = self.cycle_log_cap
+        r.phase_clock = self.phase_clock.data_ptr() if self.phase_clock is not None else None
         return r
 
     def to_host(self) -> "HostResult":

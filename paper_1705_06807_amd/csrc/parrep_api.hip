@@ -173,7 +173,7 @@ int alloc_arena(std::vector<DevInst>& insts, hipStream_t st, Arena& a, DevInst**
         sp_off[i] = off;
         off = align256(off + kSpillCap * sizeof(SpillSlot));
         x_off[i] = off;
-        off = align256(off + (size_t)insts[i].R * kMaxS * sizeof(int32_t));
+        off = align256(off + 2 * (size_t)insts[i].R * kMaxS * sizeof(int32_t));
         s_off[i] = off;
         off = align256(off + (size_t)insts[i].R * 4 * sizeof(uint64_t));
     }
@@ -214,14 +214,18 @@ int run_instances(parrep_ctx* ctx, std::vector<DevInst>& insts, LaunchShape shap
     rc = alloc_arena(insts, st, a, &d);
     if (rc) return rc;
     const int n = (int)insts.size();
-    int max_tab = 0;
-    for (const DevInst& di : insts) max_tab = std::max(max_tab, di.net.n_reactions * di.tab_L);
-    const int tab_lds = table_lds_doubles(shape, max_tab);
+    int max_L = 1, max_m = 1;
+    for (const DevInst& di : insts) {
+        max_L = std::max(max_L, di.tab_L);
+        max_m = std::max(max_m, (int)di.net.n_reactions);
+    }
+    shape.m = max_m;
+    const int tab_Ls = table_lds_states(shape, max_L);
     hipError_t e = launch_setup(d, n, st);
     if (e == hipSuccess && mode == kModeSolve) e = launch_zero(d, n, st);
     if (e == hipSuccess && ev_before) e = hipEventRecord(ev_before, st);
     if (e == hipSuccess)
-        e = launch_solve(d, n, shape, mode, hook_cycle, hook_max_rounds, tab_lds, st);
+        e = launch_solve(d, n, shape, mode, hook_cycle, hook_max_rounds, tab_Ls, st);
     if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
     if (e == hipSuccess && mode == kModeSolve) e = launch_finalize(d, n, st);
     hipError_t ef = hipFreeAsync(a.base, st);
@@ -246,6 +250,7 @@ void attach_result(DevInst& d, const parrep_result* r) {
     d.counters = r->counters;
     d.cycle_log = r->cycle_log_cap > 0 ? r->cycle_log : nullptr;
     d.cycle_log_cap = r->cycle_log_cap;
+    d.phase_clock = r->phase_clock;
 }
 
 }  // namespace
@@ -253,6 +258,14 @@ void attach_result(DevInst& d, const parrep_result* r) {
 extern "C" {
 
 const char* parrep_last_error(void) { return g_err.c_str(); }
+
+double parrep_wall_clock_hz(parrep_ctx* ctx) {
+    if (!ctx || set_device(ctx)) return 0.0;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess)
+        return 0.0;
+    return 1e3 * khz;
+}
 
 int parrep_ctx_create(int device, parrep_ctx** out) {
     if (!out) return fail(PARREP_EINVAL, "out is NULL");
@@ -358,7 +371,7 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
         maxR = std::max(maxR, probs[i].R);
         maxS = std::max(maxS, (int)nets[i]->net.n_species);
     }
-    LaunchShape shape = choose_shape(maxR, maxS);
+    LaunchShape shape = choose_shape(maxR, maxS, kMaxM);
     hipEvent_t ev_b = launch ? (hipEvent_t)launch->event_before : nullptr;
     hipEvent_t ev_a = launch ? (hipEvent_t)launch->event_after : nullptr;
     if (launch && (launch->replicas_per_lane > 0 || launch->waves > 0)) {
@@ -396,7 +409,7 @@ int parrep_events(parrep_ctx* ctx, const parrep_net* net, const double* c_host, 
     if (rc) return rc;
     std::vector<DevInst> insts(1);
     fill_inst(insts[0], net, &p, nb);
-    insts[0].tab_L = 1024;  // states from 1024 on take the formula path
+    insts[0].tab_L = 1024;  // the hook stages states below 512; the rest take the formula path
     rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -425,7 +438,7 @@ int parrep_dephase_only(parrep_ctx* ctx, const parrep_net* net, const parrep_pro
     insts[0].hook_states = Y_out;
     insts[0].hook_i64 = rounds_out;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    return run_instances(ctx, insts, choose_shape(prob->R, net->net.n_species), kModeDephaseOnly,
+    return run_instances(ctx, insts, choose_shape(prob->R, net->net.n_species, net->net.n_reactions), kModeDephaseOnly,
                          cycle, -1, (hipStream_t)stream);
 }
 
@@ -444,7 +457,7 @@ int parrep_parallel_only(parrep_ctx* ctx, const parrep_net* net, const parrep_pr
     insts[0].hook_i64 = out_i64;
     insts[0].hook_f64 = credited;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    return run_instances(ctx, insts, choose_shape(prob->R, net->net.n_species), kModeParallelOnly,
+    return run_instances(ctx, insts, choose_shape(prob->R, net->net.n_species, net->net.n_reactions), kModeParallelOnly,
                          cycle, max_rounds, (hipStream_t)stream);
 }
 

@@ -43,16 +43,15 @@ __device__ __forceinline__ Blk philox10(uint32_t c0, uint32_t c1, uint32_t c2, u
                                         uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // one 32x32->64 product each (a single v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -123,6 +122,16 @@ __device__ __forceinline__ Fx fx_from(double d) {
     r.lo = ((uint64_t)(uint32_t)ah << 32) | (uint64_t)(uint32_t)bl;
     return r;
 }
+
+// Values known to be equal in all lanes, moved to scalar registers.
+__device__ __forceinline__ uint32_t ufl(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ int ufl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t ufl64(uint64_t v) {
+    return ((uint64_t)ufl((uint32_t)(v >> 32)) << 32) | ufl((uint32_t)v);
+}
+__device__ __forceinline__ Fx ufx(Fx v) { return Fx{ufl64(v.hi), ufl64(v.lo)}; }
 
 // ---------------------------------------------------------------------------
 // Network program in LDS
@@ -287,33 +296,83 @@ __device__ __forceinline__ double lambda_formula(const DevInst* __restrict__ I, 
     return lam;
 }
 
-// lambda_j(x): constant, table entry (the LDS copy when the workgroup holds
-// one, else the global table), or the defining formula.
-template <int NS>
-__device__ __forceinline__ double lam_j(const DevInst* __restrict__ I, const double* ltab, int j,
-                                        const int (&x)[NS]) {
-    const uint32_t meta = I->jmeta[j];
-    const uint32_t kind = meta & 3u;
-    if (kind == kRxConst) return I->k[j];
-    if (kind == kRxTable) {
-        const int xs = pick<NS>(x, (int)((meta >> 2) & 3u));
-        const int L = I->tab_L;
-        if ((unsigned)xs < (unsigned)L) return ltab ? ltab[j * L + xs] : I->tab[j * L + xs];
+// Uniform per-instance network data of the event loop, loaded once per
+// phase (scalar registers): rate constants, per-reaction kind and species,
+// packed stoichiometry, and the LDS propensity tables.  M >= n_reactions;
+// reactions m..M-1 are padding with lambda = 0 (adding +0.0 to a partial sum
+// changes nothing, so the padding leaves every sum and the selection as is).
+template <int M>
+struct HotNet {
+    uint32_t stoich[M];  // packed eta_j
+    uint32_t species;    // 2 bits per reaction: the species its table is indexed by
+    int Ls;              // states 0..Ls-1 of each reaction's species are in the LDS table
+    bool any_direct;     // some reaction needs the formula at every state
+};
+
+template <int M>
+__device__ __forceinline__ HotNet<M> load_hot(const DevInst* __restrict__ I, int Ls) {
+    HotNet<M> h;
+    const int m = I->net.n_reactions;
+    h.any_direct = false;
+    uint32_t sp = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const uint32_t meta = j < m ? I->jmeta[j] : (uint32_t)kRxConst;
+        h.stoich[j] = j < m ? ufl(I->jstoich[j]) : 0u;
+        sp |= ((meta >> 2) & 3u) << (2 * j);
+        h.any_direct = h.any_direct || ((meta & 3u) == kRxDirect);
     }
-    return lambda_formula<NS>(I, j, x);
+    h.species = ufl(sp);
+    h.Ls = ufl(Ls);
+    return h;
 }
 
 // One Gillespie event at x (the "generate tau and J" step of Alg. 1):
 // tau = -log(u_open)/a0 (+inf when absorbing) and the packed change of
 // channel J = first j with u_sel*a0 < S_j, S_j the left-to-right partial
-// sums (recomputed in a second pass; the same additions give the same sums).
-template <int NS>
-__device__ __forceinline__ void ssa_event(const DevInst* __restrict__ I, const double* ltab,
-                                          const int (&x)[NS], const Blk& b, double& tau, int& J,
-                                          uint32_t& dxp, double* a0_out = nullptr) {
-    const int m = I->net.n_reactions;
+// sums.  Propensities come from the LDS tables, which hold exactly what the
+// defining formula gives; states outside the tables (rare; checked once per
+// event for the whole wave) and two-factor reactions use the formula.
+template <int NS, int M>
+__device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
+                                                    const DevInst* __restrict__ I,
+                                                    const double* __restrict__ ltab,
+                                                    const int (&x)[NS], double neglog_u_open,
+                                                    double u_sel_v, double& tau, int& J,
+                                                    uint32_t& dxp, double* a0_out = nullptr) {
+    bool inr = true;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) inr = inr && (unsigned)x[i] < (unsigned)h.Ls;
+    double cum[M];
     double s = 0.0;
-    for (int j = 0; j < m; ++j) s = s + lam_j<NS>(I, ltab, j, x);
+    uint32_t pos = 0;
+    if (__builtin_expect(__ballot(!inr) == 0ull && !h.any_direct, 1)) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
+            s = s + ltab[j * h.Ls + xs];
+            cum[j] = s;
+        }
+        // positive channels, needed only when a0 is not finite (below)
+        pos = ~0u;
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double lam;
+            const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxConst;
+            if (kind != kRxDirect && inr) {
+                const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
+                lam = ltab[j * h.Ls + xs];
+            } else if (kind == kRxConst) {
+                lam = I->k[j];
+            } else {
+                lam = lambda_formula<NS>(I, j, x);
+            }
+            if (lam > 0.0) pos |= 1u << j;
+            s = s + lam;
+            cum[j] = s;
+        }
+    }
     if (a0_out) *a0_out = s;
     if (!(s > 0.0)) {
         tau = __builtin_inf();
@@ -321,33 +380,61 @@ __device__ __forceinline__ void ssa_event(const DevInst* __restrict__ I, const d
         dxp = 0;
         return;
     }
-    tau = (-log(u_open(b))) / s;
-    const double t = u_sel(b) * s;
-    double c = 0.0;
-    int pj = -1, last_pos = -1;
+    tau = neglog_u_open / s;
+    const double t = u_sel_v * s;
+    int pj = -1;
     uint32_t d = 0;
-    for (int j = 0; j < m; ++j) {
-        const double l = lam_j<NS>(I, ltab, j, x);
-        c = c + l;
-        if (l > 0.0) last_pos = j;
-        if (pj < 0 && t < c) {
+#pragma unroll
+    for (int j = M - 1; j >= 0; --j) {
+        if (t < cum[j]) {
             pj = j;
-            d = I->jstoich[j];
+            d = h.stoich[j];
         }
     }
-    if (pj < 0) {  // only for non-finite a0: the last positive channel
-        pj = last_pos;
+    if (pj < 0) {  // only for non-finite a0: the last channel with lambda > 0
+        if (pos == ~0u) {  // table path: recompute which channels are positive
+            pos = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
+                if (ltab[j * h.Ls + xs] > 0.0) pos |= 1u << j;
+            }
+        }
+        pj = 31 - __clz(pos);
         d = I->jstoich[pj];
     }
     J = pj;
     dxp = d;
 }
 
+template <int NS, int M>
+__device__ __forceinline__ void ssa_event(const HotNet<M>& h, const DevInst* __restrict__ I,
+                                          const double* __restrict__ ltab, const int (&x)[NS],
+                                          const Blk& b, double& tau, int& J, uint32_t& dxp,
+                                          double* a0_out = nullptr) {
+    event_from_uniforms<NS, M>(h, I, ltab, x, -log(u_open(b)), u_sel(b), tau, J, dxp, a0_out);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int j) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bits, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), j);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Metastable set of x: 1 if w.x >= theta, else 0 (weights of +-1 and 0 take
+// additions only; the weights are uniform, so the branches are scalar).
 template <int NS>
 __device__ __forceinline__ int region_of(const DevInst* __restrict__ I, const int (&x)[NS]) {
     int64_t d = 0;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) d += (int64_t)I->region_w[i] * (int64_t)x[i];
+    for (int i = 0; i < NS; ++i) {
+        const int w = I->region_w[i];
+        const int64_t xi = x[i];
+        if (w == 1) d += xi;
+        else if (w == -1) d -= xi;
+        else if (w != 0) d += (int64_t)w * xi;
+    }
     return d >= I->region_theta ? 1 : 0;
 }
 
@@ -430,14 +517,6 @@ __device__ __forceinline__ bool credit_event(const DevInst* __restrict__ I, cons
     return hit;
 }
 
-__device__ __forceinline__ uint32_t ufl(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-__device__ __forceinline__ int ufl(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ uint64_t ufl64(uint64_t v) {
-    return ((uint64_t)ufl((uint32_t)(v >> 32)) << 32) | ufl((uint32_t)v);
-}
-__device__ __forceinline__ Fx ufx(Fx v) { return Fx{ufl64(v.hi), ufl64(v.lo)}; }
 
 // FIM / RER integrands at x, times weight w, added through `add(slot, value)`
 // (Sec. III and Appendix A: FIM(x) = sum_j lam_j g_j g_j^T with
@@ -497,8 +576,8 @@ struct Shared {
     int32_t flags[2][WAVES];
     int32_t wmin[2][WAVES];
     uint64_t wsum[2][WAVES][2];
-    uint64_t mask[E];
-    int32_t cnt[E];
+    uint64_t mask[2][E];
+    int32_t cnt[2][E];
     int32_t bi[16];
     uint64_t bu[8];
 };
@@ -562,23 +641,6 @@ __device__ __forceinline__ void block_min_sum(Shared<E, WAVES>& sh, int& par, in
     }
 }
 
-template <int E, int WAVES>
-__device__ __forceinline__ int block_or_flags(Shared<E, WAVES>& sh, int& par, int wid, int lane,
-                                              int bits) {
-    const int any_exit = __ballot(bits & 1) != 0ull;
-    const int any_nd = __ballot(bits & 2) != 0ull;
-    const int f = any_exit | (any_nd << 1);
-    if (WAVES == 1) return f;
-    const int p = par;
-    par ^= 1;
-    if (lane == 0) sh.flags[p][wid] = f;
-    __syncthreads();
-    int o = 0;
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) o |= sh.flags[p][w];
-    return o;
-}
-
 template <int NS>
 __device__ void log_cycle(const DevInst* I, int64_t i, int64_t cyc, int64_t s1, int64_t s2,
                           int64_t s3, int64_t K, int64_t phase, const int (&x)[NS]) {
@@ -602,6 +664,8 @@ __device__ void log_cycle(const DevInst* I, int64_t i, int64_t cyc, int64_t s1, 
 // ---------------------------------------------------------------------------
 struct RunState {
     uint64_t C_hi, C_lo;
+    uint64_t clk[4], clk_mark;  // phase wall-clock accounting (thread 0)
+    uint64_t Tq_hi, Tq_lo, tbq_hi, tbq_lo;  // horizon and burn-in time, 64.64
     int64_t ev_total;
     int64_t c_decorr, c_dephase, c_cred, c_disc, c_cycles, c_s3, c_s2, c_fv, n_log;
     int64_t s1_events;
@@ -609,12 +673,17 @@ struct RunState {
     int32_t xt[kMaxS], xend[kMaxS];
 };
 
-// S1, decorrelation (serial, thread 0): Alg. 1's loop over "generate tau and
-// J", credit, jump, count consecutive steps (or time) in the current set.
-template <int NS>
-__device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, const double* ltab,
-                                            RunState& rs, Fx Tq, Fx tbq, int64_t max_ev,
-                                            uint32_t key0, uint32_t key1) {
+// S1, decorrelation: Alg. 1's serial loop over "generate tau and J", credit,
+// jump, count consecutive steps (or time) in the current set.  Run by wave 0
+// with the state held identically in all lanes: the random numbers of the
+// next 64 steps do not depend on the state, so lane i draws step k+i's block
+// (and -log u_open) in parallel, and the serial chain only does the
+// state-dependent part.  Lane 0 does the accumulation.
+template <int NS, int M>
+__device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* __restrict__ I,
+                                            const double* __restrict__ ltab, RunState& rs, Fx Tq,
+                                            Fx tbq, int64_t max_ev, uint32_t key0, uint32_t key1,
+                                            int lane) {
     const bool steps = I->decorr_mode == PARREP_STEPS;
     const int64_t n_c = (int64_t)I->decorr;
     const double t_c = I->decorr;
@@ -628,49 +697,62 @@ __device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, const
     int64_t Nc = 0, k = 0;
     double e = 0.0;
     int stop = 0;
-    for (;;) {
-        if (steps ? (Nc >= n_c) : (e >= t_c)) break;
-        if (ev + 1 > max_ev) {
-            stop = 9;
-            break;
-        }
-        const Blk b = draw((uint64_t)k, 0u, cycle, kTagDecorr, key0, key1);
-        double tau;
-        int J;
-        uint32_t dxp;
-        ssa_event<NS>(I, ltab, x, b, tau, J, dxp);
-        ++k;
-        ++ev;
-        Fx Cn;
-        const bool hit = credit_event<NS>(I, x, tau, C, Tq, tbq, true, Cn);
-        C = Cn;
-        if (hit) {
-            stop = 1;
-            break;
-        }
-        apply_dx<NS>(x, dxp);
-        const int rg = region_of<NS>(I, x);
-        if (rg == W) {
-            Nc += 1;
-            e = e + tau;
-        } else {
-            W = rg;
-            Nc = 0;
-            e = 0.0;
+    bool fin = false;
+    while (!fin) {
+        const Blk b = draw((uint64_t)(k + lane), 0u, cycle, kTagDecorr, key0, key1);
+        const double nl_l = -log(u_open(b));
+        const double us_l = u_sel(b);
+        for (int j = 0; j < 64; ++j) {
+            if (steps ? (Nc >= n_c) : (e >= t_c)) {
+                fin = true;
+                break;
+            }
+            if (ev + 1 > max_ev) {
+                stop = 9;
+                fin = true;
+                break;
+            }
+            double tau;
+            int J;
+            uint32_t dxp;
+            event_from_uniforms<NS, M>(h, I, ltab, x, readlane_f64(nl_l, j),
+                                       readlane_f64(us_l, j), tau, J, dxp);
+            ++k;
+            ++ev;
+            Fx Cn;
+            const bool hit = credit_event<NS>(I, x, tau, C, Tq, tbq, lane == 0, Cn);
+            C = Cn;
+            if (hit) {
+                stop = 1;
+                fin = true;
+                break;
+            }
+            apply_dx<NS>(x, dxp);
+            const int rg = region_of<NS>(I, x);
+            if (rg == W) {
+                Nc += 1;
+                e = e + tau;
+            } else {
+                W = rg;
+                Nc = 0;
+                e = 0.0;
+            }
         }
     }
+    if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-        rs.xt[i] = x[i];
-        if (stop) rs.xend[i] = x[i];
+        for (int i = 0; i < NS; ++i) {
+            rs.xt[i] = x[i];
+            if (stop) rs.xend[i] = x[i];
+        }
+        rs.W = W;
+        rs.C_hi = C.hi;
+        rs.C_lo = C.lo;
+        rs.ev_total = ev;
+        rs.c_decorr += k;
+        rs.s1_events = k;
+        rs.stop = stop;
     }
-    rs.W = W;
-    rs.C_hi = C.hi;
-    rs.C_lo = C.lo;
-    rs.ev_total = ev;
-    rs.c_decorr += k;
-    rs.s1_events = k;
-    rs.stop = stop;
 }
 
 // ---------------------------------------------------------------------------
@@ -682,11 +764,11 @@ __device__ __forceinline__ void decorrelate(const DevInst* __restrict__ I, const
 template <int RPL>
 constexpr int kMinWavesPerEU = RPL == 4 ? 4 : 1;
 
-template <int NS, int RPL, int WAVES>
+template <int NS, int M, int RPL, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL>, 8)))
 k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
-           int64_t hook_max_rounds, int tab_lds_doubles) {
+           int64_t hook_max_rounds, int tab_Ls) {
     constexpr int B = 64 * WAVES;
     constexpr int E = RPL * WAVES;
     __shared__ RunState rs;
@@ -702,29 +784,39 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
     const bool accum = mode == kModeSolve;
     // Fleming-Viot exchange: LDS when the shape's replica capacity fits 32 KiB
     // (the launcher sizes dynamic LDS by the same rule), else global scratch.
-    constexpr bool kXbufLds = RPL * B * NS * 4 <= 32768;
-    constexpr int kXbufInts = kXbufLds ? RPL * B * NS : 0;
+    constexpr int kXbufRound = RPL * B * NS;  // ints per exchange buffer (two buffers)
+    constexpr bool kXbufLds = 2 * kXbufRound * 4 <= 32768;
+    constexpr int kXbufInts = kXbufLds ? 2 * kXbufRound : 0;
     int32_t* xbuf = kXbufLds ? dyn_lds : I->xbuf;
-    // Propensity tables: copied into LDS (after the exchange buffer) when the
-    // launch reserved room for them (tab_lds_doubles > 0), else read from HBM.
-    double* ltab = nullptr;
-    if (tab_lds_doubles > 0) {
-        ltab = reinterpret_cast<double*>(dyn_lds + ((kXbufInts + 1) & ~1));
-        const int nt = I->net.n_reactions * I->tab_L;
-        for (int i = tid; i < nt; i += B) ltab[i] = I->tab[i];
+    // Propensity tables: states 0..Ls-1 of each table reaction are copied into
+    // LDS after the exchange buffer (the launcher reserved M * tab_Ls doubles).
+    const int L = I->tab_L;
+    const int Ls = L < tab_Ls ? L : tab_Ls;
+    double* ltab = reinterpret_cast<double*>(dyn_lds + ((kXbufInts + 1) & ~1));
+    for (int i = tid; i < M * Ls; i += B) {
+        const int j = i / Ls;
+        const int xs = i - j * Ls;
+        const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxDirect;
+        ltab[i] = kind == kRxTable ? I->tab[j * L + xs] : (kind == kRxConst ? I->k[j] : 0.0);
     }
+    const HotNet<M> hn = load_hot<M>(I, Ls);
     const int64_t max_ev = I->max_events > 0 ? I->max_events : (int64_t(1) << 50);
-    Fx Tq = fx_from(I->T), tbq = fx_from(I->t_burn);
-    if (mode == kModeParallelOnly) {
-        Tq = Fx{~0ull, ~0ull};
-        tbq = Tq;
-    }
-    Tq = ufx(Tq);
-    tbq = ufx(tbq);
     int par = 0;
 
     if (tid == 0) {
+        Fx Tq0 = fx_from(I->T), tbq0 = fx_from(I->t_burn);
+        if (mode == kModeParallelOnly) {
+            Tq0 = Fx{~0ull, ~0ull};
+            tbq0 = Tq0;
+        }
+        rs.Tq_hi = Tq0.hi;
+        rs.Tq_lo = Tq0.lo;
+        rs.tbq_hi = tbq0.hi;
+        rs.tbq_lo = tbq0.lo;
         rs.C_hi = rs.C_lo = 0;
+        rs.clk[0] = rs.clk[1] = rs.clk[2] = 0;
+        rs.clk[3] = wall_clock64();
+        rs.clk_mark = rs.clk[3];
         rs.ev_total = 0;
         rs.c_decorr = rs.c_dephase = rs.c_cred = rs.c_disc = rs.c_cycles = 0;
         rs.c_s3 = rs.c_s2 = rs.c_fv = rs.n_log = rs.s1_events = 0;
@@ -746,7 +838,16 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         // S1: decorrelation.
         // ------------------------------------------------------------------
         if (mode == kModeSolve) {
-            if (tid == 0) decorrelate<NS>(I, ltab, rs, Tq, tbq, max_ev, key0, key1);
+            if (wid == 0) {
+                if (lane == 0) rs.clk_mark = wall_clock64();
+                decorrelate<NS, M>(hn, I, ltab, rs, Fx{rs.Tq_hi, rs.Tq_lo},
+                                   Fx{rs.tbq_hi, rs.tbq_lo}, max_ev, key0, key1, lane);
+                if (lane == 0) {
+                    const uint64_t now = wall_clock64();
+                    rs.clk[0] += now - rs.clk_mark;
+                    rs.clk_mark = now;
+                }
+            }
             __syncthreads();
             if (rs.stop) {
                 if (tid == 0) {
@@ -791,8 +892,15 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     budget = true;
                     break;
                 }
+                // Double-buffered exchange: round n publishes into buffer n&1,
+                // so one barrier per round orders every read of round n before
+                // the writes of round n+2.
+                const int p = (int)(round2 & 1);
+                // LDS buffers are sized by the shape's capacity, global ones by
+                // R (2 * R * kMaxS ints per instance).
+                int32_t* xb = xbuf + p * (kXbufLds ? kXbufRound : R * NS);
                 uint32_t exitbits = 0;
-                int bits = 0;
+                bool nd = false;
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
@@ -802,41 +910,41 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         double tau;
                         int J;
                         uint32_t dxp;
-                        ssa_event<NS>(I, ltab, Y[k], b, tau, J, dxp);
+                        ssa_event<NS, M>(hn, I, ltab, Y[k], b, tau, J, dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
-                        if (region_of<NS>(I, Y[k]) != W) {
-                            exitbits |= 1u << k;
-                            bits |= 1;
-                        }
-                        if (!(tr[k] >= t_p)) bits |= 2;
+                        if (region_of<NS>(I, Y[k]) != W) exitbits |= 1u << k;
+                        if (!(tr[k] >= t_p)) nd = true;
                     }
                 }
-                const int fl = block_or_flags<E, WAVES>(sh, par, wid, lane, bits);
-                if (fl & 1) {
+                // Publish the post-round states and the survivor masks.
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r < R) {
+#pragma unroll
+                        for (int i = 0; i < NS; ++i) xb[r * NS + i] = Y[k][i];
+                    }
+                    const bool surv = (r < R) && !((exitbits >> k) & 1u);
+                    const uint64_t m = __ballot(surv);
+                    if (lane == 0) {
+                        sh.mask[p][k * WAVES + wid] = m;
+                        sh.cnt[p][k * WAVES + wid] = __popcll(m);
+                    }
+                }
+                const bool wave_nd = __ballot(nd) != 0ull;
+                if (lane == 0) sh.flags[p][wid] = wave_nd ? 1 : 0;
+                __syncthreads();
+                int nS = 0;
+                for (int e = 0; e < E; ++e) nS += sh.cnt[p][e];
+                nS = ufl(nS);
+                int notdone = 0;
+#pragma unroll
+                for (int w = 0; w < WAVES; ++w) notdone |= sh.flags[p][w];
+                if (nS < R) {
                     // Survivors keep their post-round state; each exited
                     // replica copies the post-round state of survivor
-                    // floor(u |S| / 2^32) in ascending replica order.  The
-                    // next round's flag exchange orders these reads before
-                    // the exchange buffer is written again.
-#pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        const int r = k * B + tid;
-                        if (r < R) {
-#pragma unroll
-                            for (int i = 0; i < NS; ++i) xbuf[r * NS + i] = Y[k][i];
-                        }
-                        const bool surv = (r < R) && !((exitbits >> k) & 1u);
-                        const uint64_t m = __ballot(surv);
-                        if (lane == 0) {
-                            sh.mask[k * WAVES + wid] = m;
-                            sh.cnt[k * WAVES + wid] = __popcll(m);
-                        }
-                    }
-                    __syncthreads();
-                    int nS = 0;
-                    for (int e = 0; e < E; ++e) nS += sh.cnt[e];
-                    nS = ufl(nS);
+                    // floor(u |S| / 2^32) in ascending replica order.
                     if (exitbits) {
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
@@ -848,15 +956,15 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                                 int idx = (int)(((uint64_t)b.w0 * (uint64_t)nS) >> 32);
                                 int e = 0;
                                 for (;;) {
-                                    const int c = sh.cnt[e];
+                                    const int c = sh.cnt[p][e];
                                     if (idx < c) break;
                                     idx -= c;
                                     ++e;
                                 }
-                                const int l = select_bit(sh.mask[e], idx);
+                                const int l = select_bit(sh.mask[p][e], idx);
                                 const int rr = (e / WAVES) * B + (e % WAVES) * 64 + l;
 #pragma unroll
-                                for (int i = 0; i < NS; ++i) Y[k][i] = xbuf[rr * NS + i];
+                                for (int i = 0; i < NS; ++i) Y[k][i] = xb[rr * NS + i];
                             } else {
 #pragma unroll
                                 for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
@@ -864,13 +972,15 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         }
                     }
                     fv += R - nS;
-                    if (WAVES == 1) __syncthreads();
                 }
                 ++round2;
-                done = steps ? (round2 >= n_p) : !(fl & 2);
+                done = steps ? (round2 >= n_p) : (notdone == 0);
             }
             __syncthreads();
             if (tid == 0) {
+                const uint64_t now = wall_clock64();
+                rs.clk[1] += now - rs.clk_mark;
+                rs.clk_mark = now;
                 rs.ev_total += round2 * R;
                 rs.c_dephase += round2 * R;
                 rs.c_fv += fv;
@@ -919,6 +1029,8 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         if (mode == kModeParallelOnly && hook_max_rounds >= 0 && hook_max_rounds < budget3)
             budget3 = hook_max_rounds;
         Fx C = ufx(Fx{rs.C_hi, rs.C_lo});
+        const Fx Tq = ufx(Fx{rs.Tq_hi, rs.Tq_lo});
+        const Fx tbq = ufx(Fx{rs.tbq_hi, rs.tbq_lo});
         int64_t round3 = 0, cred = 0, disc = 0;
         int outcome = -1;  // 1 exit, 0 horizon, -1 budget
         int Kx = 0;
@@ -940,7 +1052,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     const Blk b = draw((uint64_t)round3, (uint32_t)r, cycle, kTagParallel, key0,
                                        key1);
                     int J;
-                    ssa_event<NS>(I, ltab, Y[k], b, tauk[k], J, dxk[k]);
+                    ssa_event<NS, M>(hn, I, ltab, Y[k], b, tauk[k], J, dxk[k]);
                     int post[NS];
 #pragma unroll
                     for (int i = 0; i < NS; ++i) post[i] = Y[k][i];
@@ -1077,6 +1189,9 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             return;
         }
         if (tid == 0) {
+            const uint64_t now = wall_clock64();
+            rs.clk[2] += now - rs.clk_mark;
+            rs.clk_mark = now;
             rs.ev_total += round3 * R;
             rs.c_cred += cred;
             rs.c_disc += disc;
@@ -1124,6 +1239,12 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
 #pragma unroll
         for (int i = 0; i < kMaxS; ++i) I->x_final[i] = i < NS ? rs.xend[i] : 0;
         I->stats[PARREP_ST_T] = fx_to_f64(Fx{rs.C_hi, rs.C_lo});
+        if (I->phase_clock) {
+            I->phase_clock[0] = (int64_t)rs.clk[0];
+            I->phase_clock[1] = (int64_t)rs.clk[1];
+            I->phase_clock[2] = (int64_t)rs.clk[2];
+            I->phase_clock[3] = (int64_t)(wall_clock64() - rs.clk[3]);
+        }
     }
 }
 

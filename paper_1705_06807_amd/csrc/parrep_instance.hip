@@ -15,20 +15,19 @@ namespace parrep {
 namespace dev {
 namespace {
 
-// Dynamic LDS: the Fleming-Viot exchange buffer when the shape's replica
-// capacity fits 32 KiB (the kernel applies the same rule), then, if
-// tab_doubles > 0, the propensity tables.
-template <int NS, int RPL, int WAVES>
+// Dynamic LDS: the two Fleming-Viot exchange buffers when they fit 32 KiB
+// (the kernel applies the same rule), then M * tab_Ls doubles of
+// propensity table.
+template <int NS, int M, int RPL, int WAVES>
 hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64_t hmr,
-                           int tab_doubles, hipStream_t st) {
-    constexpr size_t xints = (size_t)RPL * 64 * WAVES * NS;
+                           int tab_Ls, hipStream_t st) {
+    constexpr size_t xints = 2 * (size_t)RPL * 64 * WAVES * NS;  // two exchange buffers
     const size_t xb = xints * 4 <= 32768 ? ((xints + 1) & ~size_t(1)) * 4 : 0;
-    const size_t lds = xb + (size_t)tab_doubles * 8;
-    hipLaunchKernelGGL((k_instance<NS, RPL, WAVES>), dim3(n), dim3(64 * WAVES), lds, st, d, mode,
-                       hc, hmr, tab_doubles);
+    const size_t lds = xb + (size_t)M * tab_Ls * 8;
+    hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES>), dim3(n), dim3(64 * WAVES), lds, st, d,
+                       mode, hc, hmr, tab_Ls);
     return hipGetLastError();
 }
-
 
 }  // namespace
 }  // namespace dev
@@ -37,13 +36,21 @@ hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64
 #define PARREP_CAT(a, b, c, d) PARREP_CAT2(a, b, c, d)
 #define PARREP_FN PARREP_CAT(launch_instance_ns, PARREP_NS, _w, PARREP_WAVES)
 
-hipError_t PARREP_FN(const DevInst* d, int n, int rpl, int mode, uint32_t hc, int64_t hmr,
-                     int tab_doubles, hipStream_t st) {
+hipError_t PARREP_FN(const DevInst* d, int n, int m, int rpl, int mode, uint32_t hc, int64_t hmr,
+                     int tab_Ls, hipStream_t st) {
     constexpr int NS = PARREP_NS, WV = PARREP_WAVES;
+    if (m <= 4) {
+        switch (rpl) {
+            case 1: return dev::launch_instance<NS, 4, 1, WV>(d, n, mode, hc, hmr, tab_Ls, st);
+            case 4: return dev::launch_instance<NS, 4, 4, WV>(d, n, mode, hc, hmr, tab_Ls, st);
+            case 16: return dev::launch_instance<NS, 4, 16, WV>(d, n, mode, hc, hmr, tab_Ls, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (rpl) {
-        case 1: return dev::launch_instance<NS, 1, WV>(d, n, mode, hc, hmr, tab_doubles, st);
-        case 4: return dev::launch_instance<NS, 4, WV>(d, n, mode, hc, hmr, tab_doubles, st);
-        case 16: return dev::launch_instance<NS, 16, WV>(d, n, mode, hc, hmr, tab_doubles, st);
+        case 1: return dev::launch_instance<NS, 8, 1, WV>(d, n, mode, hc, hmr, tab_Ls, st);
+        case 4: return dev::launch_instance<NS, 8, 4, WV>(d, n, mode, hc, hmr, tab_Ls, st);
+        case 16: return dev::launch_instance<NS, 8, 16, WV>(d, n, mode, hc, hmr, tab_Ls, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -66,6 +66,7 @@ struct DevInst {
     int64_t* counters;
     int64_t* cycle_log;
     int32_t cycle_log_cap, reserved;
+    int64_t* phase_clock;  // optional: ticks in S1, S2, S3, total
     // hot-path network view (jmeta/jstoich/tab_L filled on the host from the
     // network; k and the tables computed on the device by the setup kernel)
     double k[kMaxM];          // k_j = c[rate_param] * kappa (kappa when rate_param < 0)
@@ -78,7 +79,7 @@ struct DevInst {
     // library scratch
     double* acc;         // kAccLen doubles: outside-box accumulators
     SpillSlot* spill;    // kSpillCap slots: time at states outside the histogram box
-    int32_t* xbuf;       // R * kMaxS: Fleming-Viot state exchange
+    int32_t* xbuf;       // 2 * R * kMaxS: Fleming-Viot state exchange (two rounds)
     uint64_t* sbuf;      // R * 4: boundary-round clock scan (tau, start) as 64.64
     // test-hook outputs (unused by full solves)
     int32_t* hook_states;   // dephase-only: output states; parallel-only: input states
@@ -99,15 +100,16 @@ enum : uint32_t { kRxConst = 0, kRxTable = 1, kRxDirect = 2 };
 
 struct LaunchShape {
     int rpl, waves, ns;
+    int m;  // reactions (the kernel is specialised for m <= 4 and m <= 8)
 };
 
 // Launchers (parrep_kernels.hip).
 hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, int mode,
-                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_lds_doubles,
+                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_Ls,
                         hipStream_t stream);
-// Doubles of propensity table to stage in LDS per workgroup for this shape
-// (0: read the tables from HBM).
-int table_lds_doubles(LaunchShape shape, int max_table_doubles);
+// States per reaction of propensity table the workgroup can stage in LDS for
+// this shape (beyond them the formula is evaluated).
+int table_lds_states(LaunchShape shape, int max_tab_L);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream);
@@ -116,6 +118,6 @@ hipError_t launch_events(const DevInst* d_inst, int64_t n, const int32_t* states
                          const uint32_t* blocks, double* a0, double* tau, int32_t* J,
                          hipStream_t stream);
 bool shape_supported(LaunchShape s);
-LaunchShape choose_shape(int R, int ns);
+LaunchShape choose_shape(int R, int ns, int m);
 
 }  // namespace parrep

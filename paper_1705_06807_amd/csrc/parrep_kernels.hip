@@ -118,12 +118,23 @@ __global__ void k_philox(int64_t n, const uint32_t* __restrict__ ck, uint32_t* _
     out[4 * i + 3] = b.w3;
 }
 
-__global__ void k_events(const DevInst* __restrict__ inst, int64_t n,
-                         const int32_t* __restrict__ states, const uint32_t* __restrict__ blocks,
-                         double* a0o, double* tauo, int32_t* Jo) {
-    __shared__ SNet S;
-    if (threadIdx.x == 0) load_net(S, inst);
+constexpr int kEventsHookLs = 512;
+
+__global__ void __launch_bounds__(256) k_events(const DevInst* __restrict__ inst, int64_t n,
+                                                const int32_t* __restrict__ states,
+                                                const uint32_t* __restrict__ blocks, double* a0o,
+                                                double* tauo, int32_t* Jo) {
+    __shared__ double ltab[kMaxM * kEventsHookLs];
+    const int L = inst->tab_L;
+    const int Ls = L < kEventsHookLs ? L : kEventsHookLs;
+    for (int t = threadIdx.x; t < kMaxM * Ls; t += blockDim.x) {
+        const int j = t / Ls;
+        const uint32_t kind = j < inst->net.n_reactions ? inst->jmeta[j] & 3u : (uint32_t)kRxDirect;
+        ltab[t] = kind == kRxTable ? inst->tab[j * L + (t - j * Ls)]
+                                   : (kind == kRxConst ? inst->k[j] : 0.0);
+    }
     __syncthreads();
+    const HotNet<kMaxM> hn = load_hot<kMaxM>(inst, Ls);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int x[kMaxS];
@@ -133,7 +144,7 @@ __global__ void k_events(const DevInst* __restrict__ inst, int64_t n,
     double tau, a0;
     int J;
     uint32_t dxp;
-    ssa_event<kMaxS>(inst, nullptr, x, b, tau, J, dxp, &a0);
+    ssa_event<kMaxS, kMaxM>(hn, inst, ltab, x, b, tau, J, dxp, &a0);
     a0o[i] = a0;
     tauo[i] = tau;
     Jo[i] = J;
@@ -147,34 +158,35 @@ bool shape_supported(LaunchShape s) {
     const bool ns_ok = s.ns == 1 || s.ns == 2 || s.ns == 4;
     const bool rpl_ok = s.rpl == 1 || s.rpl == 4 || s.rpl == 16;
     const bool w_ok = s.waves == 1 || s.waves == 4 || s.waves == 16;
-    return ns_ok && rpl_ok && w_ok;
+    const bool m_ok = s.m >= 1 && s.m <= kMaxM;
+    return ns_ok && rpl_ok && w_ok && m_ok;
 }
 
-LaunchShape choose_shape(int R, int ns) {
+LaunchShape choose_shape(int R, int ns, int m) {
     const int nsv = ns <= 1 ? 1 : (ns <= 2 ? 2 : 4);
-    if (R <= 64) return {1, 1, nsv};
-    if (R <= 256) return {4, 1, nsv};
-    if (R <= 1024) return {4, 4, nsv};
-    if (R <= 4096) return {4, 16, nsv};
-    return {16, 16, nsv};
+    if (R <= 64) return {1, 1, nsv, m};
+    if (R <= 256) return {4, 1, nsv, m};
+    if (R <= 1024) return {4, 4, nsv, m};
+    if (R <= 4096) return {4, 16, nsv, m};
+    return {16, 16, nsv, m};
 }
 
 #define PARREP_DECL(NSv, Wv)                                                                  \
-    hipError_t launch_instance_ns##NSv##_w##Wv(const DevInst*, int, int, int, uint32_t, int64_t, \
-                                               int, hipStream_t);
+    hipError_t launch_instance_ns##NSv##_w##Wv(const DevInst*, int, int, int, int, uint32_t,     \
+                                               int64_t, int, hipStream_t);
 PARREP_DECL(1, 1) PARREP_DECL(1, 4) PARREP_DECL(1, 16)
 PARREP_DECL(2, 1) PARREP_DECL(2, 4) PARREP_DECL(2, 16)
 PARREP_DECL(4, 1) PARREP_DECL(4, 4) PARREP_DECL(4, 16)
 #undef PARREP_DECL
 
 hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mode,
-                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_lds_doubles,
+                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_Ls,
                         hipStream_t stream) {
     if (!shape_supported(s)) return hipErrorInvalidValue;
 #define PARREP_GO(NSv, Wv)                                                                    \
     if (s.ns == NSv && s.waves == Wv)                                                         \
-        return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.rpl, mode, hook_cycle,       \
-                                               hook_max_rounds, tab_lds_doubles, stream);
+        return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.m, s.rpl, mode, hook_cycle,  \
+                                               hook_max_rounds, tab_Ls, stream);
     PARREP_GO(1, 1) PARREP_GO(1, 4) PARREP_GO(1, 16)
     PARREP_GO(2, 1) PARREP_GO(2, 4) PARREP_GO(2, 16)
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
@@ -187,12 +199,13 @@ hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream) {
     return hipGetLastError();
 }
 
-int table_lds_doubles(LaunchShape s, int max_table_doubles) {
-    const size_t xints = (size_t)s.rpl * 64 * s.waves * s.ns;
-    const size_t xb = xints * 4 <= 32768 ? xints * 4 : 0;
+int table_lds_states(LaunchShape s, int max_tab_L) {
+    const size_t xints = 2 * (size_t)s.rpl * 64 * s.waves * s.ns;
+    const size_t xb = xints * 4 <= 32768 ? ((xints + 1) & ~size_t(1)) * 4 : 0;
     const size_t budget = 56 * 1024;  // leaves room for the static LDS of the kernel
-    if (xb + (size_t)max_table_doubles * 8 > budget) return 0;
-    return max_table_doubles;
+    const int M = s.m <= 4 ? 4 : 8;
+    const size_t fit = xb < budget ? (budget - xb) / (8 * (size_t)M) : 0;
+    return (int)(fit < (size_t)max_tab_L ? fit : (size_t)max_tab_L);
 }
 
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream) {

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
     # sizes implied by the header's field lists on x86-64
     assert ctypes.sizeof(B.Factor) == 24
     assert ctypes.sizeof(B.Reaction) == 8 + 8 + 16 + 2 * 24
-    assert ctypes.sizeof(B.Result) == 6 * 8 + 8
+    assert ctypes.sizeof(B.Result) == 6 * 8 + 8 + 8
     assert ctypes.sizeof(B.Launch) == 24
     assert B.Problem.max_events.offset + 8 == ctypes.sizeof(B.Problem)
 
