@@ -11,12 +11,14 @@
 #include <vector>
 
 #include "parrep_internal.h"
+#include "parrep_neglog.h"
 
 using namespace parrep;
 
 struct parrep_ctx {
     int device = 0;
     std::mutex mu;
+    double* logtab = nullptr;  // device copy of the -log(u) reduction table
 };
 
 struct parrep_net {
@@ -81,6 +83,7 @@ int validate_problem(const parrep_net* net, const parrep_problem* p, int64_t* nb
 void fill_inst(DevInst& d, const parrep_net* net, const parrep_problem* p, int64_t nbins) {
     std::memset(&d, 0, sizeof(d));
     d.net = net->net;
+    d.logtab = net->ctx->logtab;
     const int n = d.net.n_species;
     for (int k = 0; k < kMaxP; ++k) {
         d.c[k] = k < d.net.n_params ? p->c[k] : 0.0;
@@ -276,11 +279,34 @@ int parrep_ctx_create(int device, parrep_ctx** out) {
     parrep_ctx* c = new (std::nothrow) parrep_ctx();
     if (!c) return fail(PARREP_ENOMEM, "context allocation");
     c->device = device;
+    double host_tab[kLogTabLen];
+    build_log_table(host_tab);
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc(&c->logtab, sizeof(host_tab));
+    if (e == hipSuccess) e = hipMemcpy(c->logtab, host_tab, sizeof(host_tab), hipMemcpyHostToDevice);
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (c->logtab) hipFree(c->logtab);
+        delete c;
+        return hip_fail(e, "context table upload");
+    }
     *out = c;
     return PARREP_OK;
 }
 
-void parrep_ctx_destroy(parrep_ctx* ctx) { delete ctx; }
+void parrep_ctx_destroy(parrep_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->logtab) {
+        int prev = 0;
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(ctx->device) == hipSuccess) {
+            hipFree(ctx->logtab);
+            hipSetDevice(prev);
+        }
+    }
+    delete ctx;
+}
 
 int parrep_net_create(parrep_ctx* ctx, int32_t n_species, int32_t n_reactions, int32_t n_params,
                       const parrep_reaction* rx, parrep_net** out) {
@@ -361,6 +387,7 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
     int maxR = 1, maxS = 1;
     for (int i = 0; i < count; ++i) {
         if (!nets[i]) return fail(PARREP_EINVAL, "NULL net");
+        if (nets[i]->ctx != ctx) return fail(PARREP_EINVAL, "net was created in another context");
         int64_t nb = 0;
         int rc = validate_problem(nets[i], &probs[i], &nb);
         if (rc) return rc;
@@ -398,6 +425,7 @@ int parrep_events(parrep_ctx* ctx, const parrep_net* net, const double* c_host, 
                   int32_t* J, void* stream) {
     if (!ctx || !net || !c_host || n < 0 || (n > 0 && (!states || !blocks || !a0 || !tau || !J)))
         return fail(PARREP_EINVAL, "bad argument");
+    if (net->ctx != ctx) return fail(PARREP_EINVAL, "net was created in another context");
     parrep_problem p;
     std::memset(&p, 0, sizeof(p));
     for (int k = 0; k < net->net.n_params; ++k) p.c[k] = c_host[k];
@@ -429,6 +457,7 @@ int parrep_dephase_only(parrep_ctx* ctx, const parrep_net* net, const parrep_pro
                         void* stream) {
     if (!ctx || !net || !prob || !xt || !Y_out || !rounds_out)
         return fail(PARREP_EINVAL, "NULL argument");
+    if (net->ctx != ctx) return fail(PARREP_EINVAL, "net was created in another context");
     int64_t nb = 0;
     int rc = validate_problem(net, prob, &nb);
     if (rc) return rc;
@@ -447,6 +476,7 @@ int parrep_parallel_only(parrep_ctx* ctx, const parrep_net* net, const parrep_pr
                          int64_t* out_i64, int32_t* exit_state, double* credited, void* stream) {
     if (!ctx || !net || !prob || !init || !out_i64 || !exit_state || !credited)
         return fail(PARREP_EINVAL, "NULL argument");
+    if (net->ctx != ctx) return fail(PARREP_EINVAL, "net was created in another context");
     int64_t nb = 0;
     int rc = validate_problem(net, prob, &nb);
     if (rc) return rc;

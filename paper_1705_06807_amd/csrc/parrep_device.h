@@ -25,6 +25,7 @@
 //     horizon are crossed at one event whatever the reduction order.
 #pragma once
 #include "parrep_internal.h"
+#include "parrep_neglog.h"
 
 #include <climits>
 
@@ -39,15 +40,47 @@ struct Blk {
     uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ k in one VALU op (gfx950 three-input bit operation; 0x96 is the
+// truth table of a three-way XOR), k in a scalar register.
+__device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// a * m as one 32x32->64 multiply-add with both halves in a register pair.
+__device__ __forceinline__ uint64_t mul_wide_sk(uint32_t a, uint32_t m) {
+    uint64_t r, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "v"(a), "s"(m));
+    return r;
+}
+
+// UK: the key is the same in every lane (the instance's).  Its round keys
+// are then re-derived in scalar registers at each call (hoisted out of the
+// caller's loops, the twenty of them would be spilled to vector lanes and
+// read back with one VALU op each), and from the third round on, when all
+// four words differ between lanes, each round is two multiply-adds and two
+// three-way XORs.  Rounds 0-1 are left to the compiler, which keeps the
+// words that are still lane-uniform in scalar registers.
+template <bool UK = true>
 __device__ __forceinline__ Blk philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
+    if (UK) asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        // one 32x32->64 product each (a single v_mad_u64_u32)
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint64_t p0, p1;
+        uint32_t n0, n2;
+        if (UK && i > 1) {
+            p0 = mul_wide_sk(c0, 0xD2511F53u);
+            p1 = mul_wide_sk(c2, 0xCD9E8D57u);
+            n0 = xor3_sk((uint32_t)(p1 >> 32), c1, k0);
+            n2 = xor3_sk((uint32_t)(p0 >> 32), c3, k1);
+        } else {
+            p0 = (uint64_t)0xD2511F53u * c0;
+            p1 = (uint64_t)0xCD9E8D57u * c2;
+            n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        }
         c0 = n0;
         c1 = (uint32_t)p1;
         c2 = n2;
@@ -72,6 +105,12 @@ __device__ __forceinline__ double u_open(const Blk& b) {
 __device__ __forceinline__ double u_sel(const Blk& b) {
     const uint64_t w = ((uint64_t)b.w3 << 32) | b.w2;
     return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// -log(u_open(b)); lt: the reduction table in LDS.
+__device__ __forceinline__ double neglog_u_open(const Blk& b, const double* __restrict__ lt) {
+    const uint64_t w = ((uint64_t)b.w1 << 32) | b.w0;
+    return neglog_u53((w >> 11) + 1, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -409,10 +448,12 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
 
 template <int NS, int M>
 __device__ __forceinline__ void ssa_event(const HotNet<M>& h, const DevInst* __restrict__ I,
-                                          const double* __restrict__ ltab, const int (&x)[NS],
+                                          const double* __restrict__ ltab,
+                                          const double* __restrict__ lgt, const int (&x)[NS],
                                           const Blk& b, double& tau, int& J, uint32_t& dxp,
                                           double* a0_out = nullptr) {
-    event_from_uniforms<NS, M>(h, I, ltab, x, -log(u_open(b)), u_sel(b), tau, J, dxp, a0_out);
+    event_from_uniforms<NS, M>(h, I, ltab, x, neglog_u_open(b, lgt), u_sel(b), tau, J, dxp,
+                               a0_out);
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int j) {
@@ -681,7 +722,8 @@ struct RunState {
 // state-dependent part.  Lane 0 does the accumulation.
 template <int NS, int M>
 __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* __restrict__ I,
-                                            const double* __restrict__ ltab, RunState& rs, Fx Tq,
+                                            const double* __restrict__ ltab,
+                                            const double* __restrict__ lgt, RunState& rs, Fx Tq,
                                             Fx tbq, int64_t max_ev, uint32_t key0, uint32_t key1,
                                             int lane) {
     const bool steps = I->decorr_mode == PARREP_STEPS;
@@ -700,7 +742,7 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
     bool fin = false;
     while (!fin) {
         const Blk b = draw((uint64_t)(k + lane), 0u, cycle, kTagDecorr, key0, key1);
-        const double nl_l = -log(u_open(b));
+        const double nl_l = neglog_u_open(b, lgt);
         const double us_l = u_sel(b);
         for (int j = 0; j < 64; ++j) {
             if (steps ? (Nc >= n_c) : (e >= t_c)) {
@@ -799,6 +841,8 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxDirect;
         ltab[i] = kind == kRxTable ? I->tab[j * L + xs] : (kind == kRxConst ? I->k[j] : 0.0);
     }
+    __shared__ double lgt[kLogTabLen];
+    for (int i = tid; i < kLogTabLen; i += B) lgt[i] = I->logtab[i];
     const HotNet<M> hn = load_hot<M>(I, Ls);
     const int64_t max_ev = I->max_events > 0 ? I->max_events : (int64_t(1) << 50);
     int par = 0;
@@ -840,7 +884,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         if (mode == kModeSolve) {
             if (wid == 0) {
                 if (lane == 0) rs.clk_mark = wall_clock64();
-                decorrelate<NS, M>(hn, I, ltab, rs, Fx{rs.Tq_hi, rs.Tq_lo},
+                decorrelate<NS, M>(hn, I, ltab, lgt, rs, Fx{rs.Tq_hi, rs.Tq_lo},
                                    Fx{rs.tbq_hi, rs.tbq_lo}, max_ev, key0, key1, lane);
                 if (lane == 0) {
                     const uint64_t now = wall_clock64();
@@ -910,7 +954,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         double tau;
                         int J;
                         uint32_t dxp;
-                        ssa_event<NS, M>(hn, I, ltab, Y[k], b, tau, J, dxp);
+                        ssa_event<NS, M>(hn, I, ltab, lgt, Y[k], b, tau, J, dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
                         if (region_of<NS>(I, Y[k]) != W) exitbits |= 1u << k;
@@ -1052,7 +1096,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     const Blk b = draw((uint64_t)round3, (uint32_t)r, cycle, kTagParallel, key0,
                                        key1);
                     int J;
-                    ssa_event<NS, M>(hn, I, ltab, Y[k], b, tauk[k], J, dxk[k]);
+                    ssa_event<NS, M>(hn, I, ltab, lgt, Y[k], b, tauk[k], J, dxk[k]);
                     int post[NS];
 #pragma unroll
                     for (int i = 0; i < NS; ++i) post[i] = Y[k][i];

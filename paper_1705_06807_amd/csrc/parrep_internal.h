@@ -76,6 +76,7 @@ struct DevInst {
     int32_t tab_L;            // table entries per reaction (states 0..tab_L-1)
     int32_t tab_owner;        // 1: this instance's setup block fills the table
     double* tab;              // kMaxM * tab_L propensities, shared by equal (network, c)
+    const double* logtab;     // kLogTabLen: reduction table of -log(u) (context-owned)
     // library scratch
     double* acc;         // kAccLen doubles: outside-box accumulators
     SpillSlot* spill;    // kSpillCap slots: time at states outside the histogram box

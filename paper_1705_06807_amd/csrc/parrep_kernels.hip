@@ -111,7 +111,7 @@ __global__ void k_philox(int64_t n, const uint32_t* __restrict__ ck, uint32_t* _
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t* q = ck + 6 * i;
-    const Blk b = philox10(q[0], q[1], q[2], q[3], q[4], q[5]);
+    const Blk b = philox10<false>(q[0], q[1], q[2], q[3], q[4], q[5]);
     out[4 * i] = b.w0;
     out[4 * i + 1] = b.w1;
     out[4 * i + 2] = b.w2;
@@ -133,6 +133,8 @@ __global__ void __launch_bounds__(256) k_events(const DevInst* __restrict__ inst
         ltab[t] = kind == kRxTable ? inst->tab[j * L + (t - j * Ls)]
                                    : (kind == kRxConst ? inst->k[j] : 0.0);
     }
+    __shared__ double lgt[kLogTabLen];
+    for (int t = threadIdx.x; t < kLogTabLen; t += blockDim.x) lgt[t] = inst->logtab[t];
     __syncthreads();
     const HotNet<kMaxM> hn = load_hot<kMaxM>(inst, Ls);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(256) k_events(const DevInst* __restrict__ inst
     double tau, a0;
     int J;
     uint32_t dxp;
-    ssa_event<kMaxS, kMaxM>(hn, inst, ltab, x, b, tau, J, dxp, &a0);
+    ssa_event<kMaxS, kMaxM>(hn, inst, ltab, lgt, x, b, tau, J, dxp, &a0);
     a0o[i] = a0;
     tauo[i] = tau;
     Jo[i] = J;

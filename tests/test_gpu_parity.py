@@ -21,6 +21,9 @@ from paper_1705_06807_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-12
+# tau = -log(u)/a0: the device log is within 0.8 ulp, the C library's within
+# about 0.5, and each side rounds the quotient once: 2.5 ulp in all.
+TAU_RTOL = 2.5 * 2.0 ** -52
 
 
 def _flush(msg):
@@ -101,7 +104,7 @@ def test_ssa_events(B, oracle, name):
         lam, oa0, otau, oJ, _ = oracle.event(net, c, states[i], blocks[i])
         assert a0[i] == oa0, (i, a0[i], oa0)
         assert J[i] == oJ, i
-        assert tau[i] == pytest.approx(otau, rel=4e-16, abs=0), i
+        assert tau[i] == pytest.approx(otau, rel=TAU_RTOL, abs=0), i
 
 
 C1_CASES = [
