@@ -389,7 +389,8 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
-            s = s + ltab[j * h.Ls + xs];
+            const double lam = ltab[j * h.Ls + xs];
+            s = j == 0 ? lam : s + lam;  // 0 + lam_1 = lam_1 (lam_1 >= 0)
             cum[j] = s;
         }
         // positive channels, needed only when a0 is not finite (below)
@@ -714,12 +715,26 @@ struct RunState {
     int32_t xt[kMaxS], xend[kMaxS];
 };
 
-// S1, decorrelation: Alg. 1's serial loop over "generate tau and J", credit,
-// jump, count consecutive steps (or time) in the current set.  Run by wave 0
-// with the state held identically in all lanes: the random numbers of the
-// next 64 steps do not depend on the state, so lane i draws step k+i's block
-// (and -log u_open) in parallel, and the serial chain only does the
-// state-dependent part.  Lane 0 does the accumulation.
+// S1, decorrelation (Alg. 1), run by one wave in batches of 64 steps.  Lane
+// i draws step k+i's Philox block and -log(u_open).  A uniform chain then
+// follows the jump chain alone (propensities, selection, jump, metastable
+// set) and leaves event j in lane j: its pre- and post-jump states and a0.
+// The lanes take the waiting times tau_j = -log(u_j)/a0_j and the exact 64.64
+// clock by an integer prefix scan; the horizon and the time-in-W rule
+// (summed in event order, as defined) fix how many of the batch's events
+// belong to S1, and those are credited in parallel.  Events past the end of
+// S1 leave no trace: the next draw continues at the first unused step.
+__device__ __forceinline__ Fx shfl_up_fx(Fx v, int off) {
+    return Fx{__shfl_up(v.hi, off), __shfl_up(v.lo, off)};
+}
+__device__ __forceinline__ Fx readlane_fx(Fx v, int j) {
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v.hi >> 32), j);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v.hi, j);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v.lo >> 32), j);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v.lo, j);
+    return Fx{((uint64_t)a << 32) | b, ((uint64_t)c << 32) | d};
+}
+
 template <int NS, int M>
 __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* __restrict__ I,
                                             const double* __restrict__ ltab,
@@ -739,47 +754,109 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
     int64_t Nc = 0, k = 0;
     double e = 0.0;
     int stop = 0;
-    bool fin = false;
-    while (!fin) {
+    for (;;) {
+        // before each step: the set kept long enough ends S1; then the budget
+        if (steps ? (Nc >= n_c) : (e >= t_c)) break;
+        if (ev + 1 > max_ev) {
+            stop = 9;
+            break;
+        }
         const Blk b = draw((uint64_t)(k + lane), 0u, cycle, kTagDecorr, key0, key1);
         const double nl_l = neglog_u_open(b, lgt);
         const double us_l = u_sel(b);
+
+        // The jump chain (uniform): event j's data go to lane j.
+        const int W0 = W;
+        int nb = 0;
+        double a0_l = 0.0;
+        int xpre_l[NS], xpost_l[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) xpre_l[i] = xpost_l[i] = x[i];
+        uint64_t rgmask = 0;
         for (int j = 0; j < 64; ++j) {
-            if (steps ? (Nc >= n_c) : (e >= t_c)) {
-                fin = true;
-                break;
+            if (j > 0) {
+                if (steps && Nc >= n_c) break;  // (time mode: decided below)
+                if (ev + j + 1 > max_ev) break;
             }
-            if (ev + 1 > max_ev) {
-                stop = 9;
-                fin = true;
-                break;
-            }
-            double tau;
+            double a0, tau_unused;
             int J;
             uint32_t dxp;
-            event_from_uniforms<NS, M>(h, I, ltab, x, readlane_f64(nl_l, j),
-                                       readlane_f64(us_l, j), tau, J, dxp);
-            ++k;
-            ++ev;
-            Fx Cn;
-            const bool hit = credit_event<NS>(I, x, tau, C, Tq, tbq, lane == 0, Cn);
-            C = Cn;
-            if (hit) {
-                stop = 1;
-                fin = true;
-                break;
-            }
+            event_from_uniforms<NS, M>(h, I, ltab, x, 0.0, readlane_f64(us_l, j), tau_unused, J,
+                                       dxp, &a0);
+            const bool me = lane == j;
+            a0_l = me ? a0 : a0_l;
+#pragma unroll
+            for (int i = 0; i < NS; ++i) xpre_l[i] = me ? x[i] : xpre_l[i];
             apply_dx<NS>(x, dxp);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) xpost_l[i] = me ? x[i] : xpost_l[i];
             const int rg = region_of<NS>(I, x);
-            if (rg == W) {
-                Nc += 1;
-                e = e + tau;
-            } else {
-                W = rg;
-                Nc = 0;
-                e = 0.0;
+            rgmask |= (uint64_t)rg << j;
+            if (steps) {
+                if (rg == W) {
+                    Nc += 1;
+                } else {
+                    W = rg;
+                    Nc = 0;
+                }
+            }
+            nb = j + 1;
+            if (!(a0 > 0.0)) break;  // absorbing: the horizon ends the run here
+        }
+
+        // Waiting times and the exact clock before / after each event.
+        const bool act = lane < nb;
+        const double tau_l = act ? (a0_l > 0.0 ? nl_l / a0_l : __builtin_inf()) : 0.0;
+        const Fx fx_l = act ? fx_from(tau_l) : Fx{0, 0};
+        Fx inc = fx_l;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const Fx t = shfl_up_fx(inc, off);
+            if (lane >= off) inc = fx_add(inc, t);
+        }
+        const Fx cpost_l = fx_add(C, inc);
+        const Fx cpre_l = fx_sub(cpost_l, fx_l);
+        const uint64_t hits = __ballot(act && fx_ge(cpost_l, Tq));
+        const int jh = hits ? __ffsll((unsigned long long)hits) - 1 : 64;
+        int n_eff = jh < nb ? jh + 1 : nb;
+        if (!steps) {
+            // time in the current set, in event order; the horizon (credited
+            // before the jump) comes first within an event
+            int Wc = W0;
+            for (int j = 0; j < n_eff; ++j) {
+                if (j == jh) break;
+                const int rg = (int)((rgmask >> j) & 1u);
+                if (rg == Wc) {
+                    e = e + readlane_f64(tau_l, j);
+                } else {
+                    Wc = rg;
+                    e = 0.0;
+                }
+                if (e >= t_c) {
+                    n_eff = j + 1;
+                    break;
+                }
             }
         }
+        if (lane < n_eff) {
+            Fx cn;
+            credit_event<NS>(I, xpre_l, tau_l, cpre_l, Tq, tbq, true, cn);
+        }
+        const int last = n_eff - 1;
+        ev += n_eff;
+        k += n_eff;
+        if (jh == last) {  // the horizon: the run ends before this event's jump
+            C = Tq;
+#pragma unroll
+            for (int i = 0; i < NS; ++i) x[i] = __builtin_amdgcn_readlane(xpre_l[i], last);
+            W = last > 0 ? (int)((rgmask >> (last - 1)) & 1u) : W0;
+            stop = 1;
+            break;
+        }
+        C = readlane_fx(cpost_l, last);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) x[i] = __builtin_amdgcn_readlane(xpost_l[i], last);
+        W = (int)((rgmask >> last) & 1u);
     }
     if (lane == 0) {
 #pragma unroll
@@ -824,12 +901,11 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
     const int R = I->R;
     const uint32_t key0 = I->seed, key1 = I->instance_id;
     const bool accum = mode == kModeSolve;
-    // Fleming-Viot exchange: LDS when the shape's replica capacity fits 32 KiB
-    // (the launcher sizes dynamic LDS by the same rule), else global scratch.
-    constexpr int kXbufRound = RPL * B * NS;  // ints per exchange buffer (two buffers)
-    constexpr bool kXbufLds = 2 * kXbufRound * 4 <= 32768;
-    constexpr int kXbufInts = kXbufLds ? 2 * kXbufRound : 0;
-    int32_t* xbuf = kXbufLds ? dyn_lds : I->xbuf;
+    // Fleming-Viot exchange: in LDS when the shape's slots fit 32 KiB (the
+    // launcher sizes dynamic LDS by the same rule), else global scratch.
+    constexpr size_t kXbufBytes = xbuf_lds_bytes(RPL, WAVES, NS);
+    constexpr int kXbufInts = (int)(kXbufBytes / 4);
+    int32_t* xbuf = kXbufBytes ? dyn_lds : I->xbuf;
     // Propensity tables: states 0..Ls-1 of each table reaction are copied into
     // LDS after the exchange buffer (the launcher reserved M * tab_Ls doubles).
     const int L = I->tab_L;
@@ -884,8 +960,13 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         if (mode == kModeSolve) {
             if (wid == 0) {
                 if (lane == 0) rs.clk_mark = wall_clock64();
+                // The serial chain is this workgroup's critical path while its
+                // other waves wait; raise its issue priority over the waves of
+                // other workgroups sharing the SIMD.
+                __builtin_amdgcn_s_setprio(3);
                 decorrelate<NS, M>(hn, I, ltab, lgt, rs, Fx{rs.Tq_hi, rs.Tq_lo},
                                    Fx{rs.tbq_hi, rs.tbq_lo}, max_ev, key0, key1, lane);
+                __builtin_amdgcn_s_setprio(0);
                 if (lane == 0) {
                     const uint64_t now = wall_clock64();
                     rs.clk[0] += now - rs.clk_mark;
@@ -936,13 +1017,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     budget = true;
                     break;
                 }
-                // Double-buffered exchange: round n publishes into buffer n&1,
-                // so one barrier per round orders every read of round n before
-                // the writes of round n+2.
                 const int p = (int)(round2 & 1);
-                // LDS buffers are sized by the shape's capacity, global ones by
-                // R (2 * R * kMaxS ints per instance).
-                int32_t* xb = xbuf + p * (kXbufLds ? kXbufRound : R * NS);
                 uint32_t exitbits = 0;
                 bool nd = false;
 #pragma unroll
@@ -961,34 +1036,45 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         if (!(tr[k] >= t_p)) nd = true;
                     }
                 }
-                // Publish the post-round states and the survivor masks.
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) {
-                    const int r = k * B + tid;
-                    if (r < R) {
-#pragma unroll
-                        for (int i = 0; i < NS; ++i) xb[r * NS + i] = Y[k][i];
-                    }
-                    const bool surv = (r < R) && !((exitbits >> k) & 1u);
-                    const uint64_t m = __ballot(surv);
-                    if (lane == 0) {
-                        sh.mask[p][k * WAVES + wid] = m;
-                        sh.cnt[p][k * WAVES + wid] = __popcll(m);
-                    }
-                }
+                // One barrier per round: each wave posts whether one of its
+                // replicas left W and whether one is still short of t_p.  The
+                // flags alternate between two slots, so the posts of round
+                // n+1 never meet a slow wave's reads of round n.
+                const bool wave_exit = __ballot(exitbits != 0u) != 0ull;
                 const bool wave_nd = __ballot(nd) != 0ull;
-                if (lane == 0) sh.flags[p][wid] = wave_nd ? 1 : 0;
+                if (lane == 0) sh.flags[p][wid] = (wave_nd ? 1 : 0) | (wave_exit ? 2 : 0);
                 __syncthreads();
-                int nS = 0;
-                for (int e = 0; e < E; ++e) nS += sh.cnt[p][e];
-                nS = ufl(nS);
-                int notdone = 0;
+                int fl = 0;
 #pragma unroll
-                for (int w = 0; w < WAVES; ++w) notdone |= sh.flags[p][w];
-                if (nS < R) {
-                    // Survivors keep their post-round state; each exited
-                    // replica copies the post-round state of survivor
-                    // floor(u |S| / 2^32) in ascending replica order.
+                for (int w = 0; w < WAVES; ++w) fl |= sh.flags[p][w];
+                fl = ufl(fl);
+                if (fl & 2) {
+                    // Some replica left W: exact Fleming-Viot restart.  Survivors
+                    // keep their post-round state; each exited replica copies the
+                    // post-round state of survivor floor(u |S| / 2^32), in
+                    // ascending replica order.  The exchange buffer and masks
+                    // are single: the next exit round writes them only after
+                    // that round's flag barrier, which every wave reaches after
+                    // its reads here.
+                    int32_t* xb = xbuf;
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = k * B + tid;
+                        if (r < R) {
+#pragma unroll
+                            for (int i = 0; i < NS; ++i) xb[r * NS + i] = Y[k][i];
+                        }
+                        const bool surv = (r < R) && !((exitbits >> k) & 1u);
+                        const uint64_t m = __ballot(surv);
+                        if (lane == 0) {
+                            sh.mask[0][k * WAVES + wid] = m;
+                            sh.cnt[0][k * WAVES + wid] = __popcll(m);
+                        }
+                    }
+                    __syncthreads();
+                    int nS = 0;
+                    for (int e = 0; e < E; ++e) nS += sh.cnt[0][e];
+                    nS = ufl(nS);
                     if (exitbits) {
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
@@ -1000,12 +1086,12 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                                 int idx = (int)(((uint64_t)b.w0 * (uint64_t)nS) >> 32);
                                 int e = 0;
                                 for (;;) {
-                                    const int c = sh.cnt[p][e];
+                                    const int c = sh.cnt[0][e];
                                     if (idx < c) break;
                                     idx -= c;
                                     ++e;
                                 }
-                                const int l = select_bit(sh.mask[p][e], idx);
+                                const int l = select_bit(sh.mask[0][e], idx);
                                 const int rr = (e / WAVES) * B + (e % WAVES) * 64 + l;
 #pragma unroll
                                 for (int i = 0; i < NS; ++i) Y[k][i] = xb[rr * NS + i];
@@ -1018,7 +1104,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     fv += R - nS;
                 }
                 ++round2;
-                done = steps ? (round2 >= n_p) : (notdone == 0);
+                done = steps ? (round2 >= n_p) : ((fl & 1) == 0);
             }
             __syncthreads();
             if (tid == 0) {

@@ -15,15 +15,12 @@ namespace parrep {
 namespace dev {
 namespace {
 
-// Dynamic LDS: the two Fleming-Viot exchange buffers when they fit 32 KiB
-// (the kernel applies the same rule), then M * tab_Ls doubles of
-// propensity table.
+// Dynamic LDS: the Fleming-Viot exchange buffer when it fits 32 KiB (the
+// kernel applies the same rule), then M * tab_Ls doubles of propensity table.
 template <int NS, int M, int RPL, int WAVES>
 hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64_t hmr,
                            int tab_Ls, hipStream_t st) {
-    constexpr size_t xints = 2 * (size_t)RPL * 64 * WAVES * NS;  // two exchange buffers
-    const size_t xb = xints * 4 <= 32768 ? ((xints + 1) & ~size_t(1)) * 4 : 0;
-    const size_t lds = xb + (size_t)M * tab_Ls * 8;
+    const size_t lds = xbuf_lds_bytes(RPL, WAVES, NS) + (size_t)M * tab_Ls * 8;
     hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES>), dim3(n), dim3(64 * WAVES), lds, st, d,
                        mode, hc, hmr, tab_Ls);
     return hipGetLastError();

@@ -93,6 +93,17 @@ struct DevInst {
 constexpr int kAccOutside = 0, kAccOutsideW = 1, kAccFim = 2, kAccRer = 2 + kMaxP * kMaxP,
               kAccY = kAccRer + kMaxP, kAccLen = kAccY + kMaxS;
 
+// Fleming-Viot exchange buffer of the instance kernel: one post-round state
+// per replica slot of the launch shape (rpl * 64 * waves slots, ns ints
+// each).  It lives in LDS when it fits 32 KiB, else in global scratch
+// (DevInst::xbuf); the kernel and its launchers size it by this rule.
+constexpr int xbuf_slot_ints(int rpl, int waves, int ns) { return rpl * 64 * waves * ns; }
+constexpr size_t xbuf_lds_bytes(int rpl, int waves, int ns) {
+    return (size_t)xbuf_slot_ints(rpl, waves, ns) * 4 <= 32768
+               ? (size_t)((xbuf_slot_ints(rpl, waves, ns) + 1) & ~1) * 4
+               : 0;
+}
+
 // Run modes of the instance kernel.
 enum : int32_t { kModeSolve = 0, kModeDephaseOnly = 1, kModeParallelOnly = 2 };
 

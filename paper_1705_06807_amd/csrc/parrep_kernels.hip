@@ -202,8 +202,7 @@ hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream) {
 }
 
 int table_lds_states(LaunchShape s, int max_tab_L) {
-    const size_t xints = 2 * (size_t)s.rpl * 64 * s.waves * s.ns;
-    const size_t xb = xints * 4 <= 32768 ? ((xints + 1) & ~size_t(1)) * 4 : 0;
+    const size_t xb = xbuf_lds_bytes(s.rpl, s.waves, s.ns);
     const size_t budget = 56 * 1024;  // leaves room for the static LDS of the kernel
     const int M = s.m <= 4 ? 4 : 8;
     const size_t fit = xb < budget ? (budget - xb) / (8 * (size_t)M) : 0;
