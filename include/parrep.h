@@ -95,6 +95,8 @@ enum {
 
 typedef struct parrep_ctx parrep_ctx;
 typedef struct parrep_net parrep_net;
+typedef struct parrep_plan parrep_plan;
+typedef struct parrep_server parrep_server;
 
 typedef struct {
     int32_t kind;        /* PARREP_FALLING or PARREP_HILL_REP                      */
@@ -203,6 +205,102 @@ int parrep_solve(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* p
 int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* nets,
                        const parrep_problem* probs, const parrep_result* res,
                        const parrep_launch* launch, void* stream);
+
+/* ---- Batched form: plans ------------------------------------------------
+ * A plan is a batch of instances prepared once: descriptors and scratch in
+ * device memory the plan owns, the instances grouped by launch shape (the
+ * autotuned one where parrep_autotune has run for that replica-count
+ * bucket, else the library default), each group ordered longest first, and
+ * setup / zero / the group launches (side by side) / finalize captured into
+ * one hipGraph.  Outputs go to the res[i] buffers given at creation.
+ * Problems as in parrep_solve_batch; EINVAL on invalid input, EDEVICE if a
+ * HIP call fails (nothing is left allocated then). */
+int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* nets,
+                       const parrep_problem* probs, const parrep_result* res,
+                       parrep_plan** out);
+
+/* Replace instance `index`'s problem (host, read during the call) for the
+ * following launches: the copy is enqueued on stream, so updates and
+ * launches on one stream apply in order.  Rate vector, seed, instance id,
+ * initial state, thresholds, horizon and budget may change; the histogram
+ * box and the table length (from hist_hi and x0) must not, and R may not
+ * exceed the planned replica count (EINVAL). */
+int parrep_plan_update(parrep_plan* plan, int32_t index, const parrep_problem* prob,
+                       void* stream);
+
+/* Replay the plan's graph on stream (outputs are rewritten each time). */
+int parrep_plan_launch(parrep_plan* plan, void* stream);
+
+/* Waits for the plan's last launch or update, then frees it. */
+void parrep_plan_destroy(parrep_plan* plan);
+
+/* Launch-shape autotuner: times `instances` copies of prob (instance ids
+ * prob->instance_id + i, each cut to trial_events events) for every compiled
+ * shape that holds prob->R replicas (up to 16x), keeps the fastest for R's
+ * bucket (the next power of two >= max(R, 64)), this species count and
+ * reaction class, and returns it in *chosen.  scratch: device buffers that
+ * all trial instances overwrite (their values are meaningless).  Blocking. */
+int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
+                    int32_t instances, int64_t trial_events, const parrep_result* scratch,
+                    parrep_launch* chosen);
+
+/* ---- Served form ----------------------------------------------------------
+ * A request asks for a ParRep estimate of one problem to a relative standard
+ * error: independent runs (instance ids prob.instance_id + k) pooled until
+ * the error of the pooled FIM diagonal and window integrals is at most
+ * rse_target (<= 0: exactly max_runs runs), max_runs runs are done, or
+ * event_budget events were spent (<= 0: no budget), with at least min_runs
+ * runs.  The server's worker thread admits requests in arrival order while
+ * device memory stays within the budget, and launches whatever runs are
+ * ready as one batch on a free server stream, so requests that arrive while
+ * others run overlap with them on the device.  Each run equals a plain
+ * solve of its problem. */
+typedef struct {
+    double rse_target;
+    int32_t min_runs;      /* >= 1 (the error needs two)                          */
+    int32_t max_runs;      /* >= min_runs                                         */
+    int64_t event_budget;
+} parrep_request;
+
+typedef struct {
+    int32_t runs;          /* runs pooled                                         */
+    int32_t status;        /* PARREP_OK or the error that stopped the request     */
+    double rse;            /* achieved relative standard error (NaN below 2 runs) */
+    int64_t events;        /* algorithmic events over all runs                    */
+    double latency_s;      /* submit to the last run's completion                 */
+    double iaf[PARREP_MAX_SPECIES]; /* integrated autocorrelation of x_i over the
+                              window, from the spread of the runs' window integrals:
+                              sum_k (Y_k - mean)^2 / ((T - t_burn)(runs - 1))       */
+} parrep_request_info;
+
+/* mem_budget: device bytes the server may hold for admitted requests and
+ * their in-flight runs (0: half of the free device memory); n_streams in
+ * [1, 16] batches may be in flight at once.  The server owns a worker
+ * thread; all server calls are thread-safe. */
+int parrep_server_create(parrep_ctx* ctx, size_t mem_budget, int32_t n_streams,
+                         parrep_server** out);
+
+/* Queue a request (prob and rq are copied; net must outlive the request).
+ * ENOMEM if one run alone exceeds the memory budget. */
+int parrep_server_submit(parrep_server* server, const parrep_net* net,
+                         const parrep_problem* prob, const parrep_request* rq,
+                         uint64_t* ticket);
+
+/* EBUSY while the request runs (wait = 0), else blocks until it is done.
+ * Then writes the pooled outputs to res (host or device buffers; may be
+ * NULL): hist and hist_window summed over runs; stats with the clock and
+ * the outside-box times summed and FIM, RER and window integrals averaged;
+ * counters summed (status: the largest); x_final of the last run.  info
+ * (may be NULL) describes the request.  The ticket is released (EINVAL if
+ * unknown); ECANCELLED for a cancelled request. */
+int parrep_server_poll(parrep_server* server, uint64_t ticket, const parrep_result* res,
+                       parrep_request_info* info, int32_t wait);
+
+/* Stop a request: runs in flight finish and are discarded. */
+int parrep_server_cancel(parrep_server* server, uint64_t ticket);
+
+/* Cancels what is still queued or running, waits for the device, frees all. */
+void parrep_server_destroy(parrep_server* server);
 
 /* Test hook: Philox4x32-10 blocks.  ctr_key (device, n x 6 uint32:
  * counter words 0-3 then key words 0-1) -> out (device, n x 4 uint32). */

@@ -67,6 +67,16 @@ class Launch(C.Structure):
                 ("event_before", C.c_void_p), ("event_after", C.c_void_p)]
 
 
+class Request(C.Structure):
+    _fields_ = [("rse_target", C.c_double), ("min_runs", C.c_int32), ("max_runs", C.c_int32),
+                ("event_budget", C.c_int64)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("runs", C.c_int32), ("status", C.c_int32), ("rse", C.c_double),
+                ("events", C.c_int64), ("latency_s", C.c_double), ("iaf", C.c_double * MAX_S)]
+
+
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -100,6 +110,20 @@ def lib():
                                               C.c_uint32, vp, vp, vp]
             L.parrep_parallel_only.argtypes = [vp, vp, C.POINTER(Problem), vp, C.c_uint32,
                                                C.c_int64, vp, vp, vp, vp]
+            L.parrep_plan_create.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Problem),
+                                             C.POINTER(Result), C.POINTER(vp)]
+            L.parrep_plan_update.argtypes = [vp, C.c_int32, C.POINTER(Problem), vp]
+            L.parrep_plan_launch.argtypes = [vp, vp]
+            L.parrep_plan_destroy.argtypes = [vp]
+            L.parrep_autotune.argtypes = [vp, vp, C.POINTER(Problem), C.c_int32, C.c_int64,
+                                          C.POINTER(Result), C.POINTER(Launch)]
+            L.parrep_server_create.argtypes = [vp, C.c_size_t, C.c_int32, C.POINTER(vp)]
+            L.parrep_server_submit.argtypes = [vp, vp, C.POINTER(Problem), C.POINTER(Request),
+                                               C.POINTER(C.c_uint64)]
+            L.parrep_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result),
+                                             C.POINTER(RequestInfo), C.c_int32]
+            L.parrep_server_cancel.argtypes = [vp, C.c_uint64]
+            L.parrep_server_destroy.argtypes = [vp]
             _lib = L
     return _lib
 
@@ -358,3 +382,106 @@ def parrep_parallel_only(p: W.Problem, init, cycle: int = 0, max_rounds: int = -
                                       cr.data_ptr(), _stream_ptr(stream)))
     o = o64.cpu().numpy()
     return int(o[0]), int(o[1]), ex.cpu().numpy()[:p.net.n_species], float(cr.cpu().item())
+
+
+class Plan:
+    """A batch prepared once and replayed as one hipGraph launch."""
+
+    def __init__(self, problems: Sequence[W.Problem], ctx: Optional[Context] = None,
+                 cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None):
+        self.ctx = ctx or context()
+        n = len(problems)
+        self.problems = list(problems)
+        self.outputs = outputs if outputs is not None else [Outputs(self.ctx, p, cycle_log_cap)
+                                                            for p in problems]
+        nets = (C.c_void_p * n)(*[self.ctx.net(p.net).value for p in problems])
+        ps = (Problem * n)(*[problem_struct(p) for p in problems])
+        rs = (Result * n)(*[o.struct() for o in self.outputs])
+        h = C.c_void_p()
+        _check(lib().parrep_plan_create(self.ctx.h, n, nets, ps, rs, C.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(lib().parrep_plan_launch(self.h, _stream_ptr(stream)))
+
+    def update(self, index: int, p: W.Problem, stream=None):
+        ps = problem_struct(p)
+        _check(lib().parrep_plan_update(self.h, index, C.byref(ps), _stream_ptr(stream)))
+        self.problems[index] = p
+        self.outputs[index].problem = p
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().parrep_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def parrep_autotune(p: W.Problem, instances: int = 1024, trial_events: int = 2_000_000,
+                    ctx: Optional[Context] = None):
+    """Time every compiled launch shape on copies of p; returns (replicas_per_lane, waves),
+    which later batches of the same replica-count bucket then use."""
+    ctx = ctx or context()
+    scratch = Outputs(ctx, p, cycle_log_cap=0)
+    ps = problem_struct(p)
+    rs = scratch.struct()
+    la = Launch()
+    _check(lib().parrep_autotune(ctx.h, ctx.net(p.net), C.byref(ps), instances, trial_events,
+                                 C.byref(rs), C.byref(la)))
+    return la.replicas_per_lane, la.waves
+
+
+class Server:
+    """Request loop with continuous batching (see parrep_server_create)."""
+
+    def __init__(self, ctx: Optional[Context] = None, mem_budget: int = 0, n_streams: int = 4):
+        self.ctx = ctx or context()
+        h = C.c_void_p()
+        _check(lib().parrep_server_create(self.ctx.h, mem_budget, n_streams, C.byref(h)))
+        self.h = h
+        self._problems = {}
+
+    def submit(self, p: W.Problem, rse_target: float = 0.0, min_runs: int = 1,
+               max_runs: Optional[int] = None, event_budget: int = 0) -> int:
+        rq = Request(rse_target, min_runs, max_runs if max_runs is not None else min_runs,
+                     event_budget)
+        ps = problem_struct(p)
+        t = C.c_uint64()
+        _check(lib().parrep_server_submit(self.h, self.ctx.net(p.net), C.byref(ps), C.byref(rq),
+                                          C.byref(t)))
+        self._problems[t.value] = p
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """None while running (wait=False); else (pooled HostResult, info dict)."""
+        p = self._problems[ticket]
+        out = Outputs(self.ctx, p, cycle_log_cap=0)
+        rs = out.struct()
+        info = RequestInfo()
+        rc = lib().parrep_server_poll(self.h, ticket, C.byref(rs), C.byref(info), 1 if wait else 0)
+        if rc == -5:  # PARREP_EBUSY
+            return None
+        del self._problems[ticket]
+        _check(rc)
+        return out.to_host(), {"runs": info.runs, "status": info.status, "rse": info.rse,
+                               "events": info.events, "latency_s": info.latency_s,
+                               "iaf": list(info.iaf)[:p.net.n_species]}
+
+    def cancel(self, ticket: int):
+        _check(lib().parrep_server_cancel(self.h, ticket))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().parrep_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

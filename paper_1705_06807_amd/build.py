@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libparrep.so")
-SOURCES = ["parrep_kernels.hip", "parrep_api.hip"]
+SOURCES = ["parrep_kernels.hip", "parrep_api.hip", "parrep_batch.hip", "parrep_server.hip"]
 # The instance kernel is compiled once per (species count, waves per workgroup).
 INSTANCE_VARIANTS = [(ns, w) for ns in (1, 2, 4) for w in (1, 4, 16)]
 ARCH = os.environ.get("PARREP_OFFLOAD_ARCH", "gfx950")
@@ -43,7 +43,8 @@ def build(force: bool = True, verbose: bool = False) -> str:
     for ns, w in INSTANCE_VARIANTS:
         jobs.append((inst, "parrep_instance_ns%d_w%d.o" % (ns, w),
                      ["-DPARREP_NS=%d" % ns, "-DPARREP_WAVES=%d" % w]))
-    deps = srcs + [inst, os.path.join(CSRC, "parrep_internal.h"),
+    deps = srcs + [inst, os.path.join(CSRC, "parrep_internal.h"), os.path.join(CSRC, "parrep_host.h"),
+                   os.path.join(CSRC, "parrep_neglog.h"),
                    os.path.join(CSRC, "parrep_device.h"), os.path.join(ROOT, "include", "parrep.h")]
     if not force and os.path.exists(LIB):
         if os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):

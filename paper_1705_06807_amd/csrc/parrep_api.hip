@@ -7,26 +7,17 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
-#include "parrep_internal.h"
+#include "parrep_host.h"
 #include "parrep_neglog.h"
 
 using namespace parrep;
 
-struct parrep_ctx {
-    int device = 0;
-    std::mutex mu;
-    double* logtab = nullptr;  // device copy of the -log(u) reduction table
-};
-
-struct parrep_net {
-    parrep_ctx* ctx = nullptr;
-    DevNet net{};
-};
-
-namespace {
+namespace parrep {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -40,7 +31,9 @@ int hip_fail(hipError_t e, const char* what) {
     return PARREP_EDEVICE;
 }
 
+namespace {
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+}  // namespace
 
 int validate_problem(const parrep_net* net, const parrep_problem* p, int64_t* nbins_out) {
     const DevNet& N = net->net;
@@ -135,11 +128,7 @@ void fill_inst(DevInst& d, const parrep_net* net, const parrep_problem* p, int64
     d.tab_L = std::min(8192, std::max(256, ((hi + 64 + 63) / 64) * 64));
 }
 
-// Device memory for one launch: descriptors plus per-instance scratch.
-struct Arena {
-    void* base = nullptr;
-    size_t bytes = 0;
-};
+namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -152,52 +141,68 @@ std::string table_key(const DevInst& d) {
     return k;
 }
 
-int alloc_arena(std::vector<DevInst>& insts, hipStream_t st, Arena& a, DevInst** d_insts) {
+// Offsets of each instance's scratch inside the arena.
+struct Layout {
+    size_t total = 0;
+    std::vector<size_t> tab, acc, spill, xbuf, sbuf;
+    std::vector<int> owner;
+};
+
+Layout layout(const std::vector<DevInst>& insts, bool share) {
     const size_t n = insts.size();
+    Layout L;
+    L.tab.resize(n);
+    L.acc.resize(n);
+    L.spill.resize(n);
+    L.xbuf.resize(n);
+    L.sbuf.resize(n);
+    L.owner.resize(n);
     size_t off = align256(n * sizeof(DevInst));
     std::map<std::string, size_t> tables;
-    std::vector<size_t> tab_off(n);
     for (size_t i = 0; i < n; ++i) {
-        auto it = tables.find(table_key(insts[i]));
+        auto it = share ? tables.find(table_key(insts[i])) : tables.end();
         if (it != tables.end()) {
-            tab_off[i] = it->second;
-            insts[i].tab_owner = 0;
+            L.tab[i] = it->second;
+            L.owner[i] = 0;
         } else {
-            tab_off[i] = off;
+            L.tab[i] = off;
             tables.emplace(table_key(insts[i]), off);
-            insts[i].tab_owner = 1;
+            L.owner[i] = 1;
             off = align256(off + (size_t)kMaxM * insts[i].tab_L * sizeof(double));
         }
     }
-    std::vector<size_t> acc_off(n), x_off(n), s_off(n), sp_off(n);
     for (size_t i = 0; i < n; ++i) {
-        acc_off[i] = off;
+        L.acc[i] = off;
         off = align256(off + kAccLen * sizeof(double));
-        sp_off[i] = off;
+        L.spill[i] = off;
         off = align256(off + kSpillCap * sizeof(SpillSlot));
-        x_off[i] = off;
-        off = align256(off + 2 * (size_t)insts[i].R * kMaxS * sizeof(int32_t));
-        s_off[i] = off;
+        L.xbuf[i] = off;
+        off = align256(off + (size_t)insts[i].R * kMaxS * sizeof(int32_t));
+        L.sbuf[i] = off;
         off = align256(off + (size_t)insts[i].R * 4 * sizeof(uint64_t));
     }
-    hipError_t e = hipMallocAsync(&a.base, off, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
-    a.bytes = off;
-    char* b = static_cast<char*>(a.base);
-    for (size_t i = 0; i < n; ++i) {
-        insts[i].tab = reinterpret_cast<double*>(b + tab_off[i]);
-        insts[i].acc = reinterpret_cast<double*>(b + acc_off[i]);
-        insts[i].spill = reinterpret_cast<SpillSlot*>(b + sp_off[i]);
-        insts[i].xbuf = reinterpret_cast<int32_t*>(b + x_off[i]);
-        insts[i].sbuf = reinterpret_cast<uint64_t*>(b + s_off[i]);
+    L.total = off;
+    return L;
+}
+
+// Expected work of an instance, for longest-first ordering: replicas times
+// horizon (the events of the dephasing and parallel steps scale with both).
+double work_estimate(const DevInst& d) { return (double)d.R * d.T; }
+
+}  // namespace
+
+size_t arena_bytes(std::vector<DevInst>& insts, bool share) { return layout(insts, share).total; }
+
+void place_arena(std::vector<DevInst>& insts, char* b, bool share) {
+    const Layout L = layout(insts, share);
+    for (size_t i = 0; i < insts.size(); ++i) {
+        insts[i].tab = reinterpret_cast<double*>(b + L.tab[i]);
+        insts[i].tab_owner = L.owner[i];
+        insts[i].acc = reinterpret_cast<double*>(b + L.acc[i]);
+        insts[i].spill = reinterpret_cast<SpillSlot*>(b + L.spill[i]);
+        insts[i].xbuf = reinterpret_cast<int32_t*>(b + L.xbuf[i]);
+        insts[i].sbuf = reinterpret_cast<uint64_t*>(b + L.sbuf[i]);
     }
-    *d_insts = reinterpret_cast<DevInst*>(b);
-    e = hipMemcpyAsync(b, insts.data(), n * sizeof(DevInst), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(a.base, st);
-        return hip_fail(e, "hipMemcpyAsync");
-    }
-    return PARREP_OK;
 }
 
 int set_device(parrep_ctx* ctx) {
@@ -205,36 +210,139 @@ int set_device(parrep_ctx* ctx) {
     return e == hipSuccess ? PARREP_OK : hip_fail(e, "hipSetDevice");
 }
 
-int run_instances(parrep_ctx* ctx, std::vector<DevInst>& insts, LaunchShape shape, int mode,
-                  uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t st,
-                  hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr) {
-    if (!shape_supported(shape))
-        return fail(PARREP_EUNSUPPORTED, "launch shape not compiled in");
-    int rc = set_device(ctx);
-    if (rc) return rc;
-    Arena a;
-    DevInst* d = nullptr;
-    rc = alloc_arena(insts, st, a, &d);
-    if (rc) return rc;
-    const int n = (int)insts.size();
-    int max_L = 1, max_m = 1;
-    for (const DevInst& di : insts) {
-        max_L = std::max(max_L, di.tab_L);
-        max_m = std::max(max_m, (int)di.net.n_reactions);
+int shape_bucket(int R) {
+    int b = 64;
+    while (b < R) b <<= 1;
+    return b;
+}
+
+LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m) {
+    const int nsc = ns <= 1 ? 1 : (ns <= 2 ? 2 : 4);
+    const int mc = m <= 4 ? 4 : 8;
+    auto it = ctx->tuned.find(std::make_tuple(shape_bucket(R), nsc, mc));
+    if (it != ctx->tuned.end()) {
+        LaunchShape s{it->second.first, it->second.second, nsc, mc};
+        if ((int64_t)s.rpl * s.waves * 64 >= R) return s;
     }
-    shape.m = max_m;
-    const int tab_Ls = table_lds_states(shape, max_L);
+    return choose_shape(R, nsc, mc);
+}
+
+std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
+                               std::vector<int>* order, const LaunchShape* forced) {
+    const int n = (int)insts.size();
+    std::vector<LaunchShape> sh(n);
+    for (int i = 0; i < n; ++i) {
+        const DevInst& d = insts[i];
+        if (forced) {
+            sh[i] = *forced;
+            sh[i].ns = d.net.n_species <= 1 ? 1 : (d.net.n_species <= 2 ? 2 : 4);
+            sh[i].m = d.net.n_reactions <= 4 ? 4 : 8;
+        } else {
+            sh[i] = pick_shape(ctx, d.R, d.net.n_species, d.net.n_reactions);
+        }
+    }
+    auto key = [&](int i) { return std::make_tuple(sh[i].ns, sh[i].m, sh[i].rpl, sh[i].waves); };
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        if (key(a) != key(b)) return key(a) < key(b);
+        return work_estimate(insts[a]) > work_estimate(insts[b]);
+    });
+    std::vector<DevInst> sorted(n);
+    for (int i = 0; i < n; ++i) sorted[i] = insts[ord[i]];
+    insts.swap(sorted);
+    std::vector<Group> groups;
+    for (int i = 0; i < n; ++i) {
+        const LaunchShape& s = sh[ord[i]];
+        if (groups.empty() || key(ord[i]) != key(ord[groups.back().first])) {
+            groups.push_back(Group{s, i, 0, 0});
+        }
+        groups.back().count += 1;
+    }
+    for (Group& g : groups) {
+        int max_L = 1;
+        for (int i = g.first; i < g.first + g.count; ++i) max_L = std::max(max_L, insts[i].tab_L);
+        g.tab_Ls = table_lds_states(g.shape, max_L);
+    }
+    if (order) *order = ord;
+    return groups;
+}
+
+int enqueue_batch(parrep_ctx* ctx, DevInst* d, int n, const std::vector<Group>& groups, int mode,
+                  uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t st, hipEvent_t ev_b,
+                  hipEvent_t ev_a, std::vector<hipEvent_t>* keep) {
+    for (const Group& g : groups)
+        if (!shape_supported(g.shape))
+            return fail(PARREP_EUNSUPPORTED, "launch shape not compiled in");
     hipError_t e = launch_setup(d, n, st);
     if (e == hipSuccess && mode == kModeSolve) e = launch_zero(d, n, st);
-    if (e == hipSuccess && ev_before) e = hipEventRecord(ev_before, st);
-    if (e == hipSuccess)
-        e = launch_solve(d, n, shape, mode, hook_cycle, hook_max_rounds, tab_Ls, st);
-    if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
-    if (e == hipSuccess && mode == kModeSolve) e = launch_finalize(d, n, st);
-    hipError_t ef = hipFreeAsync(a.base, st);
+    if (e == hipSuccess && ev_b) e = hipEventRecord(ev_b, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
-    return PARREP_OK;
+    if (groups.size() == 1) {
+        const Group& g = groups[0];
+        e = launch_solve(d + g.first, g.count, g.shape, mode, hook_cycle, hook_max_rounds,
+                         g.tab_Ls, st);
+    } else {
+        // Fork: group 0 on st, the others on auxiliary streams; join into st.
+        while (ctx->aux.size() + 1 < groups.size()) {
+            hipStream_t s = nullptr;
+            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+            ctx->aux.push_back(s);
+        }
+        hipEvent_t fork = nullptr;
+        e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(fork, st);
+        std::vector<hipEvent_t> joins(groups.size() - 1, nullptr);
+        for (size_t k = 0; e == hipSuccess && k < groups.size(); ++k) {
+            const Group& g = groups[k];
+            hipStream_t s = k == 0 ? st : ctx->aux[k - 1];
+            if (k > 0) e = hipStreamWaitEvent(s, fork, 0);
+            if (e == hipSuccess)
+                e = launch_solve(d + g.first, g.count, g.shape, mode, hook_cycle,
+                                 hook_max_rounds, g.tab_Ls, s);
+            if (e == hipSuccess && k > 0) {
+                e = hipEventCreateWithFlags(&joins[k - 1], hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventRecord(joins[k - 1], s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(st, joins[k - 1], 0);
+            }
+        }
+        if (keep) {
+            keep->push_back(fork);
+            for (hipEvent_t j : joins) keep->push_back(j);
+        } else {
+            if (fork) (void)hipEventDestroy(fork);
+            for (hipEvent_t j : joins)
+                if (j) (void)hipEventDestroy(j);
+        }
+    }
+    if (e == hipSuccess && ev_a) e = hipEventRecord(ev_a, st);
+    if (e == hipSuccess && mode == kModeSolve) e = launch_finalize(d, n, st);
+    return e == hipSuccess ? PARREP_OK : hip_fail(e, "kernel launch");
+}
+
+int run_batch(parrep_ctx* ctx, std::vector<DevInst>& insts, int mode, uint32_t hook_cycle,
+              int64_t hook_max_rounds, hipStream_t st, hipEvent_t ev_b, hipEvent_t ev_a,
+              const LaunchShape* forced) {
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    std::vector<Group> groups = group_batch(ctx, insts, nullptr, forced);
+    const size_t bytes = arena_bytes(insts);
+    void* base = nullptr;
+    hipError_t e = hipMallocAsync(&base, bytes, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    place_arena(insts, static_cast<char*>(base));
+    e = hipMemcpyAsync(base, insts.data(), insts.size() * sizeof(DevInst), hipMemcpyHostToDevice,
+                       st);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(base, st);
+        return hip_fail(e, "hipMemcpyAsync");
+    }
+    rc = enqueue_batch(ctx, static_cast<DevInst*>(base), (int)insts.size(), groups, mode,
+                       hook_cycle, hook_max_rounds, st, ev_b, ev_a);
+    hipError_t ef = hipFreeAsync(base, st);
+    if (rc) return rc;
+    return ef == hipSuccess ? PARREP_OK : hip_fail(ef, "hipFreeAsync");
 }
 
 int check_result(const parrep_result* r) {
@@ -256,7 +364,10 @@ void attach_result(DevInst& d, const parrep_result* r) {
     d.phase_clock = r->phase_clock;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace parrep
+
+using namespace parrep::host;
 
 extern "C" {
 
@@ -286,9 +397,9 @@ int parrep_ctx_create(int device, parrep_ctx** out) {
     if (e == hipSuccess) e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc(&c->logtab, sizeof(host_tab));
     if (e == hipSuccess) e = hipMemcpy(c->logtab, host_tab, sizeof(host_tab), hipMemcpyHostToDevice);
-    hipSetDevice(prev);
+    if (e != hipSuccess && c->logtab) (void)hipFree(c->logtab);
+    (void)hipSetDevice(prev);
     if (e != hipSuccess) {
-        if (c->logtab) hipFree(c->logtab);
         delete c;
         return hip_fail(e, "context table upload");
     }
@@ -298,12 +409,14 @@ int parrep_ctx_create(int device, parrep_ctx** out) {
 
 void parrep_ctx_destroy(parrep_ctx* ctx) {
     if (!ctx) return;
-    if (ctx->logtab) {
-        int prev = 0;
-        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(ctx->device) == hipSuccess) {
-            hipFree(ctx->logtab);
-            hipSetDevice(prev);
+    int prev = 0;
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(ctx->device) == hipSuccess) {
+        for (hipStream_t s : ctx->aux) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
         }
+        if (ctx->logtab) (void)hipFree(ctx->logtab);
+        (void)hipSetDevice(prev);
     }
     delete ctx;
 }
@@ -398,17 +511,21 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
         maxR = std::max(maxR, probs[i].R);
         maxS = std::max(maxS, (int)nets[i]->net.n_species);
     }
-    LaunchShape shape = choose_shape(maxR, maxS, kMaxM);
     hipEvent_t ev_b = launch ? (hipEvent_t)launch->event_before : nullptr;
     hipEvent_t ev_a = launch ? (hipEvent_t)launch->event_after : nullptr;
-    if (launch && (launch->replicas_per_lane > 0 || launch->waves > 0)) {
-        shape.rpl = launch->replicas_per_lane > 0 ? launch->replicas_per_lane : shape.rpl;
-        shape.waves = launch->waves > 0 ? launch->waves : shape.waves;
-        if ((int64_t)shape.rpl * shape.waves * 64 < maxR)
+    LaunchShape forced{};
+    const bool force = launch && (launch->replicas_per_lane > 0 || launch->waves > 0);
+    if (force) {
+        forced = choose_shape(maxR, maxS, kMaxM);
+        forced.rpl = launch->replicas_per_lane > 0 ? launch->replicas_per_lane : forced.rpl;
+        forced.waves = launch->waves > 0 ? launch->waves : forced.waves;
+        if ((int64_t)forced.rpl * forced.waves * 64 < maxR)
             return fail(PARREP_EINVAL, "launch shape holds fewer replicas than R");
+        if (!shape_supported(forced)) return fail(PARREP_EUNSUPPORTED, "launch shape not compiled in");
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
-    return run_instances(ctx, insts, shape, kModeSolve, 0, -1, (hipStream_t)stream, ev_b, ev_a);
+    return run_batch(ctx, insts, kModeSolve, 0, -1, (hipStream_t)stream, ev_b, ev_a,
+                     force ? &forced : nullptr);
 }
 
 int parrep_philox(parrep_ctx* ctx, int64_t n, const uint32_t* ctr_key, uint32_t* out,
@@ -441,13 +558,15 @@ int parrep_events(parrep_ctx* ctx, const parrep_net* net, const double* c_host, 
     rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    Arena a;
-    DevInst* d = nullptr;
-    rc = alloc_arena(insts, st, a, &d);
-    if (rc) return rc;
-    hipError_t e = launch_setup(d, 1, st);
+    void* base = nullptr;
+    hipError_t e = hipMallocAsync(&base, arena_bytes(insts), st);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    place_arena(insts, static_cast<char*>(base));
+    e = hipMemcpyAsync(base, insts.data(), sizeof(DevInst), hipMemcpyHostToDevice, st);
+    DevInst* d = static_cast<DevInst*>(base);
+    if (e == hipSuccess) e = launch_setup(d, 1, st);
     if (e == hipSuccess) e = launch_events(d, n, states, blocks, a0, tau, J, st);
-    hipError_t ef = hipFreeAsync(a.base, st);
+    hipError_t ef = hipFreeAsync(base, st);
     if (e != hipSuccess) return hip_fail(e, "events launch");
     return ef == hipSuccess ? PARREP_OK : hip_fail(ef, "hipFreeAsync");
 }
@@ -467,8 +586,8 @@ int parrep_dephase_only(parrep_ctx* ctx, const parrep_net* net, const parrep_pro
     insts[0].hook_states = Y_out;
     insts[0].hook_i64 = rounds_out;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    return run_instances(ctx, insts, choose_shape(prob->R, net->net.n_species, net->net.n_reactions), kModeDephaseOnly,
-                         cycle, -1, (hipStream_t)stream);
+    return run_batch(ctx, insts, kModeDephaseOnly, cycle, -1, (hipStream_t)stream, nullptr,
+                     nullptr, nullptr);
 }
 
 int parrep_parallel_only(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
@@ -487,8 +606,8 @@ int parrep_parallel_only(parrep_ctx* ctx, const parrep_net* net, const parrep_pr
     insts[0].hook_i64 = out_i64;
     insts[0].hook_f64 = credited;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    return run_instances(ctx, insts, choose_shape(prob->R, net->net.n_species, net->net.n_reactions), kModeParallelOnly,
-                         cycle, max_rounds, (hipStream_t)stream);
+    return run_batch(ctx, insts, kModeParallelOnly, cycle, max_rounds, (hipStream_t)stream,
+                     nullptr, nullptr, nullptr);
 }
 
 }  // extern "C"

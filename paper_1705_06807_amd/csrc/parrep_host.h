@@ -1,0 +1,88 @@
+// parrep_host.h -- host-side internals of libparrep shared by the C-ABI
+// translation units: handles, validation, device descriptors, scratch, and
+// the launch sequence of a batch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "parrep_internal.h"
+
+struct parrep_ctx {
+    int device = 0;
+    std::mutex mu;
+    double* logtab = nullptr;  // device copy of the -log(u) reduction table
+    // Streams (default priority) on which the launch groups of a batch run
+    // side by side; created on first use.
+    std::vector<hipStream_t> aux;
+    // Autotuned launch shapes: (replica-count bucket, species, reaction class)
+    // -> (replicas per lane, waves).
+    std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+};
+
+struct parrep_net {
+    parrep_ctx* ctx = nullptr;
+    parrep::DevNet net{};
+};
+
+namespace parrep {
+namespace host {
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+int set_device(parrep_ctx* ctx);
+
+int validate_problem(const parrep_net* net, const parrep_problem* p, int64_t* nbins_out);
+void fill_inst(DevInst& d, const parrep_net* net, const parrep_problem* p, int64_t nbins);
+int check_result(const parrep_result* r);
+void attach_result(DevInst& d, const parrep_result* r);
+
+// Device memory of one batch: the descriptor array then per-instance scratch
+// (propensity tables shared by equal (network, c, table length), outside-box
+// accumulators, spill table, exchange and scan buffers).
+// share_tables = false gives every instance a table of its own (plans, whose
+// instances may later change their rate vector).
+size_t arena_bytes(std::vector<DevInst>& insts, bool share_tables = true);
+// Points insts[i]'s scratch into base (arena_bytes of device memory); the
+// descriptors are then copied to base by the caller.
+void place_arena(std::vector<DevInst>& insts, char* base, bool share_tables = true);
+
+// Replica-count bucket used by the autotune table.
+int shape_bucket(int R);
+// Launch shape for an instance: the autotuned one when there is one, else
+// the library's default for R.
+LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m);
+
+// A batch after grouping: instances reordered so that each launch-shape
+// group is contiguous, each group's instances by decreasing expected work
+// (longest first, so the hardware's dispatch order fills the tail).
+struct Group {
+    LaunchShape shape;
+    int first, count, tab_Ls;
+};
+std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
+                               std::vector<int>* order, const LaunchShape* forced);
+
+// Enqueue setup, zero, the group launches (side by side on the context's
+// auxiliary streams, joined back into st), finalize.  d: device copy of the
+// grouped descriptors.  Events ev_b/ev_a (optional) bracket the instance
+// kernels on st.
+// The fork/join events are appended to *keep when it is given (stream
+// capture: they are destroyed after the capture ends), else destroyed once
+// enqueued.
+int enqueue_batch(parrep_ctx* ctx, DevInst* d, int n, const std::vector<Group>& groups,
+                  int mode, uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t st,
+                  hipEvent_t ev_b, hipEvent_t ev_a, std::vector<hipEvent_t>* keep = nullptr);
+
+// Whole batch with a stream-ordered arena: allocate, upload, enqueue, free.
+int run_batch(parrep_ctx* ctx, std::vector<DevInst>& insts, int mode, uint32_t hook_cycle,
+              int64_t hook_max_rounds, hipStream_t st, hipEvent_t ev_b, hipEvent_t ev_a,
+              const LaunchShape* forced);
+
+}  // namespace host
+}  // namespace parrep

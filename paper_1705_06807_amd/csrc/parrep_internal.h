@@ -125,6 +125,7 @@ int table_lds_states(LaunchShape shape, int max_tab_L);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream);
+hipError_t launch_accumulate(double* dst, const double* src, int64_t n, hipStream_t stream);
 hipError_t launch_philox(int64_t n, const uint32_t* ctr_key, uint32_t* out, hipStream_t stream);
 hipError_t launch_events(const DevInst* d_inst, int64_t n, const int32_t* states,
                          const uint32_t* blocks, double* a0, double* tau, int32_t* J,

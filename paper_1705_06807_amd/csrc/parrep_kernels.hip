@@ -107,6 +107,17 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
 // ---------------------------------------------------------------------------
 // Test hooks
 // ---------------------------------------------------------------------------
+// dst[i] += src[i] (pooling the histograms of a served request's runs;
+// runs of one request may finish on different streams, hence the atomics).
+__global__ void __launch_bounds__(256) k_accumulate(double* __restrict__ dst,
+                                                    const double* __restrict__ src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = src[i];
+        if (v != 0.0) atomicAdd(&dst[i], v);
+    }
+}
+
 __global__ void k_philox(int64_t n, const uint32_t* __restrict__ ck, uint32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -217,6 +228,14 @@ hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream) {
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream) {
     // NS of the finalize kernel only sizes the state vector; 4 covers all.
     hipLaunchKernelGGL((k_finalize<kMaxS>), dim3(n_inst), dim3(256), 0, stream, d_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(double* dst, const double* src, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_accumulate, dim3(blocks), dim3(256), 0, stream, dst, src, n);
     return hipGetLastError();
 }
 

@@ -34,7 +34,10 @@ def test_header_declares_the_boundary():
     for n in ("parrep_ctx_create", "parrep_ctx_destroy", "parrep_last_error", "parrep_net_create",
               "parrep_net_destroy", "parrep_solve", "parrep_solve_batch", "parrep_philox",
               "parrep_events", "parrep_dephase_only", "parrep_parallel_only",
-              "parrep_problem_nbins"):
+              "parrep_problem_nbins", "parrep_plan_create", "parrep_plan_update",
+              "parrep_plan_launch", "parrep_plan_destroy", "parrep_autotune",
+              "parrep_server_create", "parrep_server_submit", "parrep_server_poll",
+              "parrep_server_cancel", "parrep_server_destroy"):
         assert n in names
 
 
@@ -49,6 +52,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(B.Reaction) == 8 + 8 + 16 + 2 * 24
     assert ctypes.sizeof(B.Result) == 6 * 8 + 8 + 8
     assert ctypes.sizeof(B.Launch) == 24
+    assert ctypes.sizeof(B.Request) == 8 + 4 + 4 + 8
+    assert ctypes.sizeof(B.RequestInfo) == 4 + 4 + 8 + 8 + 8 + 4 * 8
     assert B.Problem.max_events.offset + 8 == ctypes.sizeof(B.Problem)
 
 
