@@ -67,6 +67,78 @@ def cpu_baseline(seconds: float, threads: int, T_sample: float):
                       "%d threads, %.1f s wall" % (n, T_sample, threads, dt)}
 
 
+def forms(B, W, ctx, args):
+    """Batched and served forms on mixed workloads with short horizons (so
+    that the plain one-at-a-time baseline stays affordable): solves/s of a
+    hipGraph plan vs sequential plain solves, and a Poisson request stream
+    served with continuous batching (p50/p99 request latency)."""
+    import numpy as np
+    import torch
+
+    Tf = args.forms_T
+    probs = W.c3_batch(seed=0, n_schlogl=128, n_toggle=128, T_schlogl=Tf, T_toggle=Tf)
+    plan = B.Plan(probs, ctx=ctx)
+    plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.launch()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    batched = len(probs) / t_batch
+    plan.close()
+    def plain_rate(ps):
+        t0 = time.perf_counter()
+        for p in ps:
+            B.parrep_solve(p, ctx=ctx, cycle_log_cap=0)
+            torch.cuda.synchronize()
+        return len(ps) / (time.perf_counter() - t0)
+
+    sample = probs[::16]
+    plain = plain_rate(sample)
+    log("forms: batched %.1f solves/s, plain %.2f solves/s" % (batched, plain))
+
+    # served: Poisson arrivals at 0.8 x the batched capacity in requests/s
+    runs_min, runs_max = 4, 16
+    rate = 0.8 * batched / (0.5 * (runs_min + runs_max))
+    arrivals, reqs = W.c5_requests(seed=0, n=args.serve_requests, rate=rate, T_schlogl=Tf,
+                                   T_toggle=Tf)
+    srv = B.Server(ctx=ctx, n_streams=4)
+    t_start = time.perf_counter()
+    tickets = []
+    for a, p in zip(arrivals, reqs):
+        dt = t_start + a - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(p, rse_target=0.02, min_runs=runs_min, max_runs=runs_max))
+    infos = [srv.poll(t)[1] for t in tickets]
+    t_serve = time.perf_counter() - t_start
+    srv.close()
+    plain_c5 = plain_rate(reqs[::6])
+    lat = np.array([i["latency_s"] for i in infos])
+    runs = int(sum(i["runs"] for i in infos))
+    met = sum(1 for i in infos if i["rse"] <= 0.02)
+    return {
+        "workload": "C3 mix (128 Schloegl c x logU[0.9,1.1], 128 toggle Omega~U{25..100}, "
+                    "R~logU[64,4096]) and C5 stream (Schloegl / toggle Omega~U{25..150}, "
+                    "R~logU[256,16384]), both with horizon T=%g" % Tf,
+        "batched_solves_per_s": batched,
+        "plain_solves_per_s": plain,
+        "batched_over_plain": batched / plain,
+        "plain_sample": "%d of the 256 instances solved one at a time" % len(sample),
+        "served": {
+            "requests": len(infos), "arrival_rate_per_s": rate,
+            "runs": runs, "solves_per_s": runs / t_serve,
+            "plain_solves_per_s": plain_c5,
+            "plain_sample": "%d of the requests' first runs solved one at a time" % len(reqs[::6]),
+            "served_over_plain": (runs / t_serve) / plain_c5,
+            "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)),
+            "rse_target": 0.02, "runs_per_request": [runs_min, runs_max],
+            "met_target": met,
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +152,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-T", type=float, default=1000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched / served measurement")
+    ap.add_argument("--forms-T", type=float, default=200.0)
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--phase-clock", action="store_true",
                     help="report where each trajectory's workgroup spent its time")
     args = ap.parse_args()
@@ -100,6 +177,14 @@ def main():
     B.lib()
     ctx = B.context(0)
     probs = [W.c2_toggle(seed=0, instance_id=i, T=args.T) for i in range(args.instances)]
+    shape = None
+    if args.rpl == 0 and args.waves == 0 and not args.no_autotune:
+        # untimed: pick the launch shape for R = 1024 on copies cut to 2e6 events
+        t = time.perf_counter()
+        shape = B.parrep_autotune(probs[0].replace(instance_id=1 << 30), instances=1024,
+                                  trial_events=2_000_000, ctx=ctx)
+        log("autotune: replicas_per_lane=%d waves=%d (%.1f s)" % (shape[0], shape[1],
+                                                                   time.perf_counter() - t))
     outs = [B.Outputs(ctx, p, cycle_log_cap=0, phase_clock=args.phase_clock) for p in probs]
     ev_b = torch.cuda.Event(enable_timing=True)
     ev_a = torch.cuda.Event(enable_timing=True)
@@ -157,6 +242,8 @@ def main():
                         "t_c=t_p=1.0, T=%g, burn-in T/2, hist [0,400]^2, FIM+RER(a1,a2,beta,gamma); "
                         "%d independent trajectories per step" % (args.T, args.instances),
             "instances": args.instances,
+            "launch_shape": ({"replicas_per_lane": shape[0], "waves": shape[1], "autotuned": True}
+                             if shape else {"replicas_per_lane": args.rpl, "waves": args.waves}),
             "replicas": 1024,
             "horizon": args.T,
         },
@@ -184,6 +271,8 @@ def main():
             "decorrelation": pc[:, 0].mean().item(), "dephasing": pc[:, 1].mean().item(),
             "parallel": pc[:, 2].mean().item(), "total_mean": tot.mean().item(),
             "total_max": tot.max().item(), "total_min": tot.min().item()}
+    if not args.no_forms:
+        line["forms"] = forms(B, W, ctx, args)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log("cpu baseline: %d threads, ~%.0f s" % (threads, args.cpu_seconds))

@@ -126,21 +126,21 @@ double pooled_rse(const Req& r) {
     return worst;
 }
 
-// Runs a request still wants launched: a first wave of min_runs, then, once
-// a wave has finished and the error is above target, enough runs to meet it
-// at the observed spread (at least one), within max_runs and the budget.
-int next_wave(Req& r) {
+// Total runs a request should have launched by now: the first min_runs;
+// once they have finished and the error is above target, as many as meet it
+// at the observed spread (done * (rse/target)^2), within max_runs and the
+// event budget.  Follow-up runs start as soon as the first min_runs have
+// finished, while later ones may still be running.
+int wanted_runs(const Req& r) {
     const parrep_request& q = r.rq;
-    if (r.done < q.min_runs) return q.min_runs - r.done;
-    if (r.done >= q.max_runs) return 0;
-    if (q.event_budget > 0 && r.events >= q.event_budget) return 0;
-    if (!(q.rse_target > 0.0)) return q.max_runs - r.done;
-    if (r.rse <= q.rse_target) return 0;
-    double want = std::isfinite(r.rse) ? std::ceil(r.done * ((r.rse / q.rse_target) *
-                                                             (r.rse / q.rse_target) - 1.0))
-                                       : (double)q.min_runs;
-    want = std::max(1.0, std::min(want, (double)(q.max_runs - r.done)));
-    return (int)want;
+    if (r.done < q.min_runs) return std::max(r.launched, q.min_runs);
+    if (q.event_budget > 0 && r.events >= q.event_budget) return r.launched;
+    if (!(q.rse_target > 0.0)) return std::max(r.launched, q.max_runs);
+    if (!std::isfinite(r.rse)) return std::max(r.launched, std::min(q.max_runs, 2));
+    if (r.rse <= q.rse_target) return r.launched;
+    const double ratio = r.rse / q.rse_target;
+    const double need = std::ceil(r.done * ratio * ratio);
+    return std::max(r.launched, (int)std::min(need, (double)q.max_runs));
 }
 
 void finish(parrep_server* s, Req& r, int status) {
@@ -187,18 +187,20 @@ void complete(parrep_server* s, Batch& b) {
             touched.push_back(pr.first);
     for (Req* rp : touched) {
         Req& r = *rp;
-        if (r.inflight > 0) continue;
-        if (r.state == Req::ACTIVE && r.done == r.wave_target) {
-            r.rse = pooled_rse(r);
-            const int more = next_wave(r);
-            if (more > 0) {
-                r.wave_target = r.done + more;
+        if (r.state == Req::ACTIVE) {
+            if (r.done >= r.rq.min_runs) r.rse = pooled_rse(r);
+            const int w = r.done >= r.rq.min_runs ? wanted_runs(r) : r.wave_target;
+            if (w > r.wave_target) {
+                r.wave_target = w;
                 if (std::find(s->ready.begin(), s->ready.end(), &r) == s->ready.end())
                     s->ready.push_back(&r);
-            } else {
+            } else if (r.inflight == 0 && r.launched == r.wave_target) {
                 finish(s, r, PARREP_OK);
             }
-        } else if (r.state == Req::CANCELLED || r.state == Req::FAILED) {
+            continue;
+        }
+        if (r.inflight > 0) continue;
+        if (r.state == Req::CANCELLED || r.state == Req::FAILED) {
             if (r.state == Req::CANCELLED) release_pool(s, r);
             if (r.forgotten) {
                 release_pool(s, r);

@@ -249,11 +249,15 @@ def c3_batch(seed: int = 0, n_schlogl: int = 128, n_toggle: int = 128,
     return out
 
 
+REQUEST_ID_STRIDE = 4096
+
+
 def c5_requests(seed: int = 0, n: int = 64, rate: float = 10.0, r_lo: int = 256,
                 r_hi: int = 16384, omega_lo: int = 25, omega_hi: int = 150,
                 T_schlogl: float = 200.0, T_toggle: float = 2e4):
     """Poisson request stream: returns (arrival_times, problems); 50% Schloegl with
-    perturbed c, 50% toggle; the request id is the Philox instance id."""
+    perturbed c, 50% toggle.  Request i's runs take Philox instance ids
+    i * REQUEST_ID_STRIDE + k, so requests never share a stream."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=n)
     arrivals = np.cumsum(gaps) - gaps[0]
@@ -263,8 +267,10 @@ def c5_requests(seed: int = 0, n: int = 64, rate: float = 10.0, r_lo: int = 256,
         if rng.uniform() < 0.5:
             f = np.exp(rng.uniform(math.log(0.9), math.log(1.1), size=4))
             c = tuple(float(a * b) for a, b in zip(SCHLOGL_CLASSIC_C, f))
-            probs.append(c1_schlogl(seed=seed, instance_id=i, R=R, T=T_schlogl).replace(c=c))
+            probs.append(c1_schlogl(seed=seed, instance_id=i * REQUEST_ID_STRIDE, R=R,
+                                    T=T_schlogl).replace(c=c))
         else:
             om = int(rng.integers(omega_lo, omega_hi + 1))
-            probs.append(c2_toggle(seed=seed, instance_id=i, omega=float(om), R=R, T=T_toggle))
+            probs.append(c2_toggle(seed=seed, instance_id=i * REQUEST_ID_STRIDE, omega=float(om),
+                                   R=R, T=T_toggle))
     return arrivals, probs
