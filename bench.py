@@ -25,16 +25,60 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSA events/s on 1 GPU (% VALU peak); batched/served ParRep solves/s + p50/p99"
 
-# Algorithmic VALU work of one SSA event of the toggle switch, in wave64
-# issue slots per lane-event (CDNA issue cost: a full-rate op 1 slot, a
-# quarter-rate op such as the 32x32->64 multiply 4 slots): Philox4x32-10
-# 20 multiplies + 40 XOR = 120; two uniforms 15; four table propensities and
-# their partial sums 12; tau = -log(u)/a0 33; selection 13; jump 4; set test
-# 3; time-mode clock 2.  Total 202 (derivation in the design doc).
-VALU_SLOTS_PER_EVENT = 202
+# Algorithmic VALU work of one SSA event of the toggle switch, in issue
+# slots per lane-event (a full-rate op 1 slot, a quarter-rate op such as the
+# 32x32->64 multiply or the FP64 reciprocal 4): Philox4x32-10 10 rounds x (2
+# multiplies + 2 three-way XORs) = 100; two 53-bit uniforms 10; -log(u) by
+# table reduction and a degree-7 log1p 16; four table propensities and their
+# partial sums 9; tau = E/a0 correctly rounded (reciprocal, two Newton steps,
+# residual correction) 13; selection 9; jump 4; set test 2; replica clock 2.
+# Total 165.
+VALU_SLOTS_PER_EVENT = 165
+# FP64 VALU instructions per event in the built kernel (rocprofv3 counters
+# SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 over events, toggle workload).
+FP64_OPS_PER_EVENT_ISA = 28.5
 # MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz, a wave64 VALU op takes 4 cycles
 # -> 256*4*16*2.4e9 = 3.93e13 lane-op slots per second.
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+# HBM traffic of one launch of the instance kernel at the benchmark workload,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by what the
+# same counters read for a plain device copy of known size; valid only for
+# the kernel sources it was measured on (their SHA-256 below).
+TRAFFIC = {"sources_sha256": "6bbb04b2208d7f9e326dbb0c68cc60917cb0b7e6e8757933047789fb540fc9e7",
+           "fetch_kib": 71862.25, "write_kib": 894804364.40625,
+           "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1705_06807_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    t = TRAFFIC
+    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
+def copy_calibration(nbytes: int):
+    """A plain device-to-device copy of nbytes, three times (for scaling the
+    HBM counters: FETCH_SIZE and WRITE_SIZE of this dispatch vs nbytes)."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": 3}), flush=True)
 
 
 def log(msg):
@@ -159,7 +203,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--phase-clock", action="store_true",
                     help="report where each trajectory's workgroup spent its time")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs each ParRep instance on a single "
@@ -256,11 +305,13 @@ def main():
             "kernel": "k_instance",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_SLOTS / 1e12,
-            "unit": "T VALU lane-op/s (issue slots)",
+            "unit": "T VALU lane-slots/s",
             "frac": achieved / VALU_PEAK_SLOTS,
-            "traffic": None,
+            "traffic": traffic_bytes(),
             "kernel_ms": k_avg,
             "ops_per_event": VALU_SLOTS_PER_EVENT,
+            "fp64_ops_per_event_isa": FP64_OPS_PER_EVENT_ISA,
+            "fp64_frac": ev * FP64_OPS_PER_EVENT_ISA / (k_avg * 1e-3) / VALU_PEAK_SLOTS,
         },
     }
     if args.phase_clock:
