@@ -3,7 +3,7 @@
 
 Workload (one step): a batch of independent ParRep trajectories of the
 two-gene toggle switch (Omega = 50, a1 = a2 = 3, beta = gamma = 2, R = 1024
-replicas, t_c = t_p = 1.0 time units, horizon T = 2e4, burn-in T/2, 2-D
+replicas, t_c = t_p = 20 time units, horizon T = 2e4, burn-in T/2, 2-D
 stationary histogram over [0,400]^2, FIM and RER w.r.t. (a1, a2, beta, gamma)),
 seeds = instance ids, all inputs synthetic.  The paper estimates its
 stationary and sensitivity quantities from many independent trajectories, so
@@ -107,7 +107,7 @@ def cpu_baseline(seconds: float, threads: int, T_sample: float):
             n += threads
     dt = time.perf_counter() - t0
     return {"value": events / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": "%d toggle trajectories (Omega=50, R=1024, t_c=t_p=1) with T cut to %g, "
+            "sample": "%d toggle trajectories (Omega=50, R=1024, t_c=t_p=20) with T cut to %g, "
                       "%d threads, %.1f s wall" % (n, T_sample, threads, dt)}
 
 
@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=4096,
+    ap.add_argument("--instances", type=int, default=8192,
                     help="independent trajectories per step")
     ap.add_argument("--T", type=float, default=2e4)
     ap.add_argument("--rpl", type=int, default=0, help="replicas per lane (0 = library choice)")
@@ -288,7 +288,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "toggle switch Omega=50 (a1=a2=3, beta=gamma=2), R=1024, "
-                        "t_c=t_p=1.0, T=%g, burn-in T/2, hist [0,400]^2, FIM+RER(a1,a2,beta,gamma); "
+                        "t_c=t_p=20, T=%g, burn-in T/2, hist [0,400]^2, FIM+RER(a1,a2,beta,gamma); "
                         "%d independent trajectories per step" % (args.T, args.instances),
             "instances": args.instances,
             "launch_shape": ({"replicas_per_lane": shape[0], "waves": shape[1], "autotuned": True}

@@ -101,7 +101,7 @@ def test_plan_update(B):
 
 def test_autotune_then_parity(B, oracle):
     import torch
-    p = W.c2_toggle(seed=4, omega=5.0, R=200, T=40.0).replace(hist_hi=(40, 40))
+    p = W.c2_toggle(seed=4, omega=5.0, R=200, T=40.0, t_cp=1.0).replace(hist_hi=(40, 40))
     rpl, waves = B.parrep_autotune(p, instances=64, trial_events=50000)
     _flush("autotuned shape for R=200: rpl=%d waves=%d" % (rpl, waves))
     assert rpl * waves * 64 >= 200
@@ -120,7 +120,7 @@ def _pooled_alone(B, p, runs):
 
 def test_server_results_alone_and_in_the_mix(B):
     reqs = [(W.c1_schlogl(seed=3, instance_id=10 * i, T=30.0), 3) for i in range(3)]
-    reqs += [(W.c2_toggle(seed=5, instance_id=10 * i, omega=5.0, R=R, T=30.0)
+    reqs += [(W.c2_toggle(seed=5, instance_id=10 * i, omega=5.0, R=R, T=30.0, t_cp=1.0)
               .replace(hist_hi=(40, 40)), 2) for i, R in enumerate((64, 700, 3000))]
     srv = B.Server(n_streams=4)
     tickets = [srv.submit(p, min_runs=n, max_runs=n) for p, n in reqs]

@@ -132,8 +132,10 @@ def test_schlogl_solve_parity(B, oracle, case):
 
 
 def _toggle_small(i, **kw):
-    # Omega = 5 switches every ~12 time units: many cycles, exits and FV restarts
-    p = W.c2_toggle(seed=11, instance_id=i, omega=5.0, R=kw.pop("R", 64), T=kw.pop("T", 300.0))
+    # Omega = 5 switches every ~12 time units: with t_c = t_p = 1, many cycles,
+    # exits and FV restarts
+    p = W.c2_toggle(seed=11, instance_id=i, omega=5.0, R=kw.pop("R", 64), T=kw.pop("T", 300.0),
+                    t_cp=1.0)
     kw.setdefault("hist_hi", (40, 40))
     return p.replace(**kw)
 
@@ -146,7 +148,8 @@ TOGGLE_CASES = [
     ("om5_steps", lambda i: _toggle_small(i, decorr_mode=W.STEPS, decorr=50,
                                           dephase_mode=W.STEPS, dephase=40)),
     ("om5_outside_box", lambda i: _toggle_small(i, hist_lo=(2, 0), hist_hi=(12, 9))),
-    ("om50_R1024", lambda i: W.c2_toggle(seed=12, instance_id=i, T=20.0)),
+    ("om50_R1024", lambda i: W.c2_toggle(seed=12, instance_id=i, T=20.0, t_cp=1.0)),
+    ("om50_R1024_t20", lambda i: W.c2_toggle(seed=13, instance_id=i, T=120.0)),
 ]
 
 

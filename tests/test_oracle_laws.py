@@ -28,7 +28,7 @@ def toggle5_pi():
 
 
 def _toggle5(seed, R, T, **kw):
-    return W.c2_toggle(seed=seed, omega=5.0, R=R, T=T).replace(hist_hi=(N5, N5), **kw)
+    return W.c2_toggle(seed=seed, omega=5.0, R=R, T=T, t_cp=1.0).replace(hist_hi=(N5, N5), **kw)
 
 
 def test_ssa_poisson_law(oracle):
