@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=8192,
+    ap.add_argument("--instances", type=int, default=16384,
                     help="independent trajectories per step")
     ap.add_argument("--T", type=float, default=2e4)
     ap.add_argument("--rpl", type=int, default=0, help="replicas per lane (0 = library choice)")

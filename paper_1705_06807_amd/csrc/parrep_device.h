@@ -58,10 +58,12 @@ __device__ __forceinline__ uint64_t mul_wide_sk(uint32_t a, uint32_t m) {
 // UK: the key is the same in every lane (the instance's).  Its round keys
 // are then re-derived in scalar registers at each call (hoisted out of the
 // caller's loops, the twenty of them would be spilled to vector lanes and
-// read back with one VALU op each), and from the third round on, when all
+// read back with one VALU op each), and from the fourth round on, when all
 // four words differ between lanes, each round is two multiply-adds and two
-// three-way XORs.  Rounds 0-1 are left to the compiler, which keeps the
-// words that are still lane-uniform in scalar registers.
+// three-way XORs.  With a lane-uniform step, cycle and tag (the replica index
+// is the only word that differs), one product of rounds 1 and 2 and both of
+// round 0 are lane-uniform: rounds 0-2 are left to the compiler, which keeps
+// those words in scalar registers.
 template <bool UK = true>
 __device__ __forceinline__ Blk philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
@@ -70,7 +72,7 @@ __device__ __forceinline__ Blk philox10(uint32_t c0, uint32_t c1, uint32_t c2, u
     for (int i = 0; i < 10; ++i) {
         uint64_t p0, p1;
         uint32_t n0, n2;
-        if (UK && i > 1) {
+        if (UK && i > 2) {
             p0 = mul_wide_sk(c0, 0xD2511F53u);
             p1 = mul_wide_sk(c2, 0xCD9E8D57u);
             n0 = xor3_sk((uint32_t)(p1 >> 32), c1, k0);
@@ -878,10 +880,11 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
 // The instance kernel: one workgroup runs Alg. 1 for one instance.
 // ---------------------------------------------------------------------------
 // Occupancy target per shape: with 4 replicas per lane the allocator is
-// asked to fit 4 waves per SIMD (at most 128 VGPRs); other shapes fit their
-// natural size.
+// asked to fit 5 waves per SIMD (at most 96 VGPRs; the few spills fall
+// outside the per-event path), which is also what the LDS of a 4-wave
+// workgroup allows (5 x 28.6 KB); other shapes fit their natural size.
 template <int RPL>
-constexpr int kMinWavesPerEU = RPL == 4 ? 4 : 1;
+constexpr int kMinWavesPerEU = RPL == 4 ? 5 : 1;
 
 template <int NS, int M, int RPL, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
