@@ -105,8 +105,11 @@ __device__ __forceinline__ double u_open(const Blk& b) {
 }
 
 __device__ __forceinline__ double u_sel(const Blk& b) {
-    const uint64_t w = ((uint64_t)b.w3 << 32) | b.w2;
-    return (double)(w >> 11) * 0x1.0p-53;
+    // (w >> 11) 2^-53 as hi 2^-21 + lo 2^-53 with hi = w3 >> 11 and lo the next
+    // 32 bits: both terms and their sum are exact
+    const uint32_t hi = b.w3 >> 11;
+    const uint32_t lo = (b.w3 << 21) | (b.w2 >> 11);
+    return fma((double)hi, 0x1.0p-21, (double)lo * 0x1.0p-53);
 }
 
 // -log(u_open(b)); lt: the reduction table in LDS.
@@ -345,9 +348,12 @@ __device__ __forceinline__ double lambda_formula(const DevInst* __restrict__ I, 
 template <int M>
 struct HotNet {
     uint32_t stoich[M];  // packed eta_j
+    uint64_t spack;      // M == 4: eta_j (species 0-1 as int8) in bits 16j..16j+15
     uint32_t species;    // 2 bits per reaction: the species its table is indexed by
     int Ls;              // states 0..Ls-1 of each reaction's species are in the LDS table
     bool any_direct;     // some reaction needs the formula at every state
+    int32_t w[kMaxS];    // metastable set: {x : w.x >= theta}
+    int64_t theta;
 };
 
 template <int M>
@@ -365,7 +371,24 @@ __device__ __forceinline__ HotNet<M> load_hot(const DevInst* __restrict__ I, int
     }
     h.species = ufl(sp);
     h.Ls = ufl(Ls);
+    uint64_t pk = 0;
+#pragma unroll
+    for (int j = 0; j < M && j < 4; ++j) pk |= (uint64_t)(h.stoich[j] & 0xFFFFu) << (16 * j);
+    h.spack = ufl64(pk);
+#pragma unroll
+    for (int i = 0; i < kMaxS; ++i) h.w[i] = ufl(I->region_w[i]);
+    h.theta = (int64_t)ufl64((uint64_t)I->region_theta);
     return h;
+}
+
+// Metastable set of x: 1 if w.x >= theta (one 32x32->64 multiply-add per
+// species, weights in scalar registers).
+template <int NS, int M>
+__device__ __forceinline__ int region_hot(const HotNet<M>& h, const int (&x)[NS]) {
+    int64_t d = 0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) d += (int64_t)h.w[i] * (int64_t)x[i];
+    return d >= h.theta ? 1 : 0;
 }
 
 // One Gillespie event at x (the "generate tau and J" step of Alg. 1):
@@ -386,7 +409,6 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
     for (int i = 0; i < NS; ++i) inr = inr && (unsigned)x[i] < (unsigned)h.Ls;
     double cum[M];
     double s = 0.0;
-    uint32_t pos = 0;
     if (__builtin_expect(__ballot(!inr) == 0ull && !h.any_direct, 1)) {
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -395,8 +417,6 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
             s = j == 0 ? lam : s + lam;  // 0 + lam_1 = lam_1 (lam_1 >= 0)
             cum[j] = s;
         }
-        // positive channels, needed only when a0 is not finite (below)
-        pos = ~0u;
     } else {
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -410,8 +430,7 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
             } else {
                 lam = lambda_formula<NS>(I, j, x);
             }
-            if (lam > 0.0) pos |= 1u << j;
-            s = s + lam;
+            s = j == 0 ? lam : s + lam;
             cum[j] = s;
         }
     }
@@ -424,23 +443,45 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
     }
     tau = neglog_u_open / s;
     const double t = u_sel_v * s;
-    int pj = -1;
-    uint32_t d = 0;
+    // With at most two species and four reactions every eta_j fits 16 bits
+    // of one 64-bit scalar: J is found by counting and eta_J by a shift.
+    constexpr bool kNarrow = NS <= 2 && M == 4;
+    int pj;
+    uint32_t d;
+    if (kNarrow) {
+        // partial sums do not decrease, so the first j with t < S_j is the
+        // number of S_j <= t; zero channels (S_j = S_{j-1}) are skipped
+        pj = 0;
 #pragma unroll
-    for (int j = M - 1; j >= 0; --j) {
-        if (t < cum[j]) {
-            pj = j;
-            d = h.stoich[j];
+        for (int j = 0; j < M - 1; ++j) pj += t >= cum[j] ? 1 : 0;
+        d = (uint32_t)(h.spack >> (16 * pj)) & 0xFFFFu;
+        if (!(t < cum[M - 1])) pj = -1;  // only for non-finite a0
+    } else {
+        pj = -1;
+        d = 0;
+#pragma unroll
+        for (int j = M - 1; j >= 0; --j) {
+            if (t < cum[j]) {
+                pj = j;
+                d = h.stoich[j];
+            }
         }
     }
     if (pj < 0) {  // only for non-finite a0: the last channel with lambda > 0
-        if (pos == ~0u) {  // table path: recompute which channels are positive
-            pos = 0;
+        uint32_t pos = 0;
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
+        for (int j = 0; j < M; ++j) {
+            double lam;
+            const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxConst;
+            if (kind != kRxDirect && inr) {
                 const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
-                if (ltab[j * h.Ls + xs] > 0.0) pos |= 1u << j;
+                lam = ltab[j * h.Ls + xs];
+            } else if (kind == kRxConst) {
+                lam = I->k[j];
+            } else {
+                lam = lambda_formula<NS>(I, j, x);
             }
+            if (lam > 0.0) pos |= 1u << j;
         }
         pj = 31 - __clz(pos);
         d = I->jstoich[pj];
@@ -792,7 +833,7 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
             apply_dx<NS>(x, dxp);
 #pragma unroll
             for (int i = 0; i < NS; ++i) xpost_l[i] = me ? x[i] : xpost_l[i];
-            const int rg = region_of<NS>(I, x);
+            const int rg = region_hot<NS, M>(h, x);
             rgmask |= (uint64_t)rg << j;
             if (steps) {
                 if (rg == W) {
@@ -1035,7 +1076,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         ssa_event<NS, M>(hn, I, ltab, lgt, Y[k], b, tau, J, dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
-                        if (region_of<NS>(I, Y[k]) != W) exitbits |= 1u << k;
+                        if (region_hot<NS, M>(hn, Y[k]) != W) exitbits |= 1u << k;
                         if (!(tr[k] >= t_p)) nd = true;
                     }
                 }
@@ -1190,7 +1231,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
 #pragma unroll
                     for (int i = 0; i < NS; ++i) post[i] = Y[k][i];
                     apply_dx<NS>(post, dxk[k]);
-                    if (region_of<NS>(I, post) != W && lfirst == INT_MAX) lfirst = r;
+                    if (region_hot<NS, M>(hn, post) != W && lfirst == INT_MAX) lfirst = r;
                     lsum = fx_add(lsum, fx_from(tauk[k]));
                 }
             }

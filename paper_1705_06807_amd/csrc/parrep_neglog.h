@@ -9,7 +9,8 @@
 // log(1/invc) split as logc_hi (a multiple of 2^-44) + logc_lo.  Then
 //     log u = k ln2 + log(1/invc) + log1p(r),  r = z*invc - 1,  |r| < 2^-7,
 // with k*ln2_hi + logc_hi exact (all terms multiples of 2^-44 below 2^6) and
-// log1p by its Taylor series to r^7 (truncation below 2^-59 absolute).  The
+// log1p by its Taylor series to r^7 (truncation below 2^-59 absolute),
+// evaluated in Estrin form.  The
 // two sub-intervals next to z = 1 use invc = 1, log c = 0, so u -> 1 keeps
 // full relative accuracy and u = 1 gives -0.0 as the C library log does.
 #pragma once
@@ -43,12 +44,14 @@ PARREP_HD inline double neglog_u53(uint64_t m, const double* __restrict__ lt) {
     const double kd = (double)k;
     const double a = std::fma(kd, kLn2Hi, lt[kLogTabN + i]);  // exact
     const double s1 = std::fma(kd, kLn2Lo, lt[2 * kLogTabN + i]);
-    double q = std::fma(r, 1.0 / 7.0, -1.0 / 6.0);
-    q = std::fma(q, r, 1.0 / 5.0);
-    q = std::fma(q, r, -0.25);
-    q = std::fma(q, r, 1.0 / 3.0);
-    q = std::fma(q, r, -0.5);
-    const double p = std::fma(r * r, q, r);
+    // q(r) = -1/2 + r/3 - r^2/4 + r^3/5 - r^4/6 + r^5/7 in Estrin form (the
+    // same terms; shorter dependency chains, no accumulator copies)
+    const double r2 = r * r;
+    const double qa = std::fma(r, 1.0 / 3.0, -0.5);
+    const double qb = std::fma(r, 1.0 / 5.0, -0.25);
+    const double qc = std::fma(r, 1.0 / 7.0, -1.0 / 6.0);
+    const double q = std::fma(r2, std::fma(r2, qc, qb), qa);
+    const double p = std::fma(r2, q, r);
     return -(a + (s1 + p));
 }
 
