@@ -1,0 +1,113 @@
+"""The paper's Schloegl experiment (Sec. IV A, Tables II-III) through the GPU
+path: V = 25, c = (3, 0.6, 0.25, 2.95), W+ = {x <= 25.96}, ParRep with
+n_c = n_p = 5000 transitions and R = 100 replicas, N = 100 trajectories of
+T = 2e5 with burn-in 1e5.  The multi-run estimators of Sec. III (mean
+pathwise FIM with 95% half-widths, the IAF of f = x from the spread of the
+window integrals, the bounds sqrt(IAF * FIM_kk)) are checked against the
+exact closed forms and, as context, printed next to the paper's values."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import exact_laws as E
+from paper_1705_06807_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden():
+    g = {}
+    for line in open(os.path.join(HERE, "golden", "paper_schlogl_v25.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v, hw = line.split()[:3]
+        g[k] = (float(v), None if hw == "-" else float(hw))
+    return g
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_06807_amd import binding
+    binding.lib()
+    return binding
+
+
+def test_paper_schlogl_tables(B):
+    import torch
+    N, T = 100, 2e5
+    probs = [W.paper_schlogl_problem(seed=0, instance_id=i, T=T).replace(t_burn=T / 2)
+             for i in range(N)]
+    print("paper Schloegl: %d trajectories, T=%g, n_c=n_p=5000, R=100" % (N, T), flush=True)
+    outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+    torch.cuda.synchronize()
+    hs = [o.to_host() for o in outs]
+    assert all(h.T_s == T and h.counters["spill_overflow"] == 0 for h in hs)
+    fim = np.array([np.diag(h.fim) for h in hs])            # (N, 4)
+    y = np.array([h.y[0] for h in hs])                      # window integrals of x
+    m = fim.mean(axis=0)
+    hw = 1.96 * fim.std(axis=0, ddof=1) / math.sqrt(N)
+    iaf = ((y - y.mean()) ** 2).sum() / ((T - T / 2) * (N - 1))
+    bounds = np.sqrt(iaf * m)
+
+    V = 25.0
+    c = np.array(W.SCHLOGL_PAPER_C)
+    x = np.arange(401)
+    pi = E.schlogl_paper_pi(400, V=V)
+    lam = E.schlogl_paper_rates(x, V=V)
+    fim_exact = np.array([np.dot(pi, lam[k]) / c[k] ** 2 for k in range(4)])
+    iaf_exact = E.birth_death_iaf(pi, lam[0] + lam[2], x.astype(float))
+    mean_exact = float(np.dot(pi, x))
+    H = sum(h.hist for h in hs)
+    mean_gpu = float(np.dot(H, np.arange(len(H)))) / (H.sum() + sum(h.outside for h in hs))
+
+    g = _golden()
+    print("%-8s %-22s %-12s %-16s" % ("", "GPU (95% half-width)", "exact", "paper"))
+    for k in range(4):
+        pv, phw = g["fim_%d%d" % (k + 1, k + 1)]
+        print("FIM_%d%d   %10.5g +- %-9.3g %-12.6g %g +- %g" % (k + 1, k + 1, m[k], hw[k],
+                                                               fim_exact[k], pv, phw))
+    print("IAF      %-22.4g %-12.4g %g" % (iaf, iaf_exact, g["iaf_x"][0]))
+    for k in range(4):
+        print("bound_c%d %-22.4g %-12.4g %g" % (k + 1, bounds[k], math.sqrt(iaf_exact * fim_exact[k]),
+                                               g["bound_c%d" % (k + 1)][0]))
+    print("E[x]     %-22.6g %-12.6g" % (mean_gpu, mean_exact), flush=True)
+
+    # FIM_33 = b V / c3 on every trajectory (the c3 channel is constant)
+    assert np.allclose(fim[:, 2], fim_exact[2], rtol=1e-9)
+    # the other diagonal entries: within 4 half-widths of the exact values
+    for k in (0, 1, 3):
+        assert abs(m[k] - fim_exact[k]) < 4 * hw[k] + 1e-12, k
+    # IAF from N = 100 runs: relative standard error about sqrt(2/99) = 14%
+    assert abs(iaf / iaf_exact - 1.0) < 0.45
+    # the stationary mean (the paper reports 0.04% error for this setting)
+    assert abs(mean_gpu / mean_exact - 1.0) < 0.005
+
+
+def test_paper_schlogl_speedup_vs_replicas(B):
+    """Speedup as defined in Sec. II B (serial computational time over
+    ParRep's), counted in SSA steps on R ideal processors: the serial SSA
+    executes the credited events, ParRep the serial decorrelation steps plus
+    one step per dephasing and parallel round.  The paper reports 7x at
+    R = 20 rising to 20x at R = 100 (n_c = n_p = 5000)."""
+    import torch
+    N, T = 20, 1e5
+    sp = {}
+    for R in (20, 50, 100):
+        probs = [W.paper_schlogl_problem(seed=1, instance_id=i, R=R, T=T) for i in range(N)]
+        outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+        torch.cuda.synchronize()
+        c = np.array([o.counters.cpu().numpy() for o in outs]).sum(axis=0)
+        serial = c[0] + c[2]                 # decorrelation + credited parallel-step events
+        parrep = c[0] + c[6] + c[5]          # decorrelation steps + S2 rounds + S3 rounds
+        sp[R] = serial / parrep
+        print("R=%3d: speedup %.1f (cycles %d)" % (R, sp[R], c[4]), flush=True)
+    assert sp[20] < sp[50] < sp[100]
+    assert sp[100] > 10.0
