@@ -26,14 +26,14 @@ sys.path.insert(0, ROOT)
 METRIC = "SSA events/s on 1 GPU (% VALU peak); batched/served ParRep solves/s + p50/p99"
 
 # Algorithmic VALU work of one SSA event of the toggle switch, in issue
-# slots per lane-event (a full-rate op 1 slot, a quarter-rate op such as the
-# 32x32->64 multiply or the FP64 reciprocal 4): Philox4x32-10 10 rounds x (2
-# multiplies + 2 three-way XORs) = 100; two 53-bit uniforms 10; -log(u) by
-# table reduction and a degree-7 log1p 16; four table propensities and their
-# partial sums 9; tau = E/a0 correctly rounded (reciprocal, two Newton steps,
-# residual correction) 13; selection 9; jump 4; set test 2; replica clock 2.
-# Total 165.
-VALU_SLOTS_PER_EVENT = 165
+# slots per lane-event (a full-rate op 1 slot; on gfx950 the 32x32->64
+# multiply-add is full rate, measured, and the FP64 reciprocal quarter rate,
+# 4 slots): Philox4x32-10 10 rounds x (2 multiply-adds + 2 three-way XORs)
+# = 40; two 53-bit uniforms 10; -log(u) by table reduction and a degree-7
+# log1p 16; four table propensities and their partial sums 9; tau = E/a0
+# correctly rounded (reciprocal, two Newton steps, residual correction) 13;
+# selection 9; jump 4; set test 2; replica clock 2.  Total 105.
+VALU_SLOTS_PER_EVENT = 105
 # FP64 VALU instructions per event in the built kernel (rocprofv3 counters
 # SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 over events, toggle workload).
 FP64_OPS_PER_EVENT_ISA = 28.5

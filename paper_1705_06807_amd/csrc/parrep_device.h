@@ -571,8 +571,16 @@ __device__ __forceinline__ void add_credit(const DevInst* __restrict__ I, const 
                                            double full, double w) {
     const int64_t idx = hist_index<NS>(I, x);
     if (idx >= 0) {
-        atomicAdd(&I->hist[idx], full);
-        if (w > 0.0) atomicAdd(&I->hist_w[idx], w);
+        // Until the finalize kernel adds the window histogram to it, hist
+        // holds only the time before t_burn: one atomic per credit except
+        // for the interval that straddles t_burn (w <= full always).
+        if (w > 0.0) {
+            atomicAdd(&I->hist_w[idx], w);
+            const double pre = full - w;
+            if (pre > 0.0) atomicAdd(&I->hist[idx], pre);
+        } else {
+            atomicAdd(&I->hist[idx], full);
+        }
     } else {
         spill_credit<NS>(I, x, full, w);
     }
@@ -606,8 +614,16 @@ __device__ __forceinline__ bool credit_event(const DevInst* __restrict__ I, cons
 // FIM / RER integrands at x, times weight w, added through `add(slot, value)`
 // (Sec. III and Appendix A: FIM(x) = sum_j lam_j g_j g_j^T with
 // g_j = grad_c log lam_j; RER_k(x) = sum_j lam_j log(lam_j/lam'_j) - lam_j + lam'_j).
-template <int NS, class Add>
-__device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, Add add) {
+// Per-thread sums of the window accumulators (compile-time indexed, so they
+// stay in registers): FIM, RER and window integrals.
+struct WinAcc {
+    double fim[kMaxP * kMaxP];
+    double rer[kMaxP];
+    double y[kMaxS];
+};
+
+template <int NS>
+__device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, WinAcc& A) {
     const int np = S.np;
     for (int j = 0; j < S.m; ++j) {
         const double lam = prop_with<NS>(S, j, x, S.c);
@@ -630,11 +646,16 @@ __device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, Add a
             for (int p = 0; p < kMaxP; ++p)
                 if (p == hp) g[p] += d;
         }
-        for (int a = 0; a < np; ++a)
-            for (int bb = 0; bb < np; ++bb) add(kAccFim + a * np + bb, w * (lam * g[a] * g[bb]));
+#pragma unroll
+        for (int a = 0; a < kMaxP; ++a)
+#pragma unroll
+            for (int bb = 0; bb < kMaxP; ++bb)
+                if (a < np && bb < np) A.fim[a * kMaxP + bb] += w * (lam * g[a] * g[bb]);
     }
     if (S.use_rer) {
-        for (int kp = 0; kp < np; ++kp) {
+#pragma unroll
+        for (int kp = 0; kp < kMaxP; ++kp) {
+            if (kp >= np) continue;
             double cv[kMaxP];
 #pragma unroll
             for (int p = 0; p < kMaxP; ++p) cv[p] = (p == kp) ? S.ceps[p] : S.c[p];
@@ -645,12 +666,12 @@ __device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, Add a
                 if (lam > 0.0) h += lam * log(lam / lp) - lam + lp;
                 else h += lp;
             }
-            add(kAccRer + kp, w * h);
+            A.rer[kp] += w * h;
         }
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i)
-        if (i < S.n) add(kAccY + i, w * (double)x[i]);
+        if (i < S.n) A.y[i] += w * (double)x[i];
 }
 
 // ---------------------------------------------------------------------------

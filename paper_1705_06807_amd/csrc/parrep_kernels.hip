@@ -65,6 +65,16 @@ __global__ void k_zero(const DevInst* __restrict__ insts) {
 // (the integrands depend on the state only, so int F(X_s) ds over the
 // window is sum_x hist_w(x) F(x)), plus the out-of-box accumulators.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Per instance: completes the full histogram (hist held the time before
+// t_burn, see add_credit), and integrates the FIM, RER and window integrals
+// over the window histogram and the spill table.  Each thread sums its bins
+// in registers; waves reduce by shuffles and add into LDS once.
 template <int NS>
 __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ insts) {
     __shared__ SNet S;
@@ -74,14 +84,22 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
     if (tid == 0) load_net(S, I);
     for (int i = tid; i < kAccLen; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
+    WinAcc A;
+#pragma unroll
+    for (int i = 0; i < kMaxP * kMaxP; ++i) A.fim[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxP; ++i) A.rer[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxS; ++i) A.y[i] = 0.0;
     for (int64_t idx = tid; idx < I->nbins; idx += blockDim.x) {
         const double h = I->hist_w[idx];
         if (h == 0.0) continue;
+        I->hist[idx] += h;
         int x[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i)
             x[i] = S.hist_lo[i] + (int)((idx / S.hist_stride[i]) % S.hist_nb[i]);
-        fim_rer_point<NS>(S, x, h, [](int slot, double v) { atomicAdd(&acc[slot], v); });
+        fim_rer_point<NS>(S, x, h, A);
     }
     // states outside the box: their window time sits in the spill table
     for (int i = tid; i < kSpillCap; i += blockDim.x) {
@@ -90,12 +108,32 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
         int x[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) x[s] = (int)((sl.key >> (15 * s)) & 0x7FFF);
-        fim_rer_point<NS>(S, x, sl.w, [](int slot, double v) { atomicAdd(&acc[slot], v); });
+        fim_rer_point<NS>(S, x, sl.w, A);
+    }
+    const int np = S.np;
+    const bool lead = (tid & 63) == 0;
+#pragma unroll
+    for (int a = 0; a < kMaxP; ++a)
+#pragma unroll
+        for (int b = 0; b < kMaxP; ++b) {
+            if (a >= np || b >= np) continue;
+            const double v = wave_sum_f64(A.fim[a * kMaxP + b]);
+            if (lead) atomicAdd(&acc[kAccFim + a * np + b], v);
+        }
+#pragma unroll
+    for (int a = 0; a < kMaxP; ++a) {
+        if (a >= np) continue;
+        const double v = wave_sum_f64(A.rer[a]);
+        if (lead) atomicAdd(&acc[kAccRer + a], v);
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxS; ++i) {
+        const double v = wave_sum_f64(A.y[i]);
+        if (lead) atomicAdd(&acc[kAccY + i], v);
     }
     __syncthreads();
     if (tid == 0) {
         const double win = I->T - I->t_burn;
-        const int np = S.np;
         I->stats[PARREP_ST_OUTSIDE] = I->acc[kAccOutside];
         I->stats[PARREP_ST_OUTSIDE_W] = I->acc[kAccOutsideW];
         for (int a = 0; a < np * np; ++a) I->stats[PARREP_ST_FIM + a] = acc[kAccFim + a] / win;
