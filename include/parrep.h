@@ -55,11 +55,17 @@ typedef enum {
 } parrep_status;
 
 /* Propensity factor kinds.  A reaction's propensity (Sec. I A) is
- *   lambda_j(x) = k_j * phi_1(x) * phi_2(x) * ...   (multiplied left to right)
- *   k_j = c[rate_param] * kappa   (k_j = kappa when rate_param < 0)
- * PARREP_FALLING:  phi = x_s (x_s-1) ... (x_s-order+1)    (mass action)
- * PARREP_HILL_REP: phi = 1 / (1 + (x_s / K)^c[hill_param]) (repression)  */
-enum { PARREP_FALLING = 0, PARREP_HILL_REP = 1 };
+ *   lambda_j(x) = k_j * phi_1(x) * phi_2(x) * ...   (state factors, left to right)
+ *   k_j = c[rate_param] * kappa * c[p_1] * ...     (PARREP_PARAM factors, left to right;
+ *                                                   c[rate_param] omitted when < 0)
+ * PARREP_FALLING:     phi = x_s (x_s-1) ... (x_s-order+1)     (mass action)
+ * PARREP_HILL_REP:    phi = 1 / (1 + (x_s / K)^c[hill_param])  (repression)
+ * PARREP_HILL_SWITCH: phi = c[hill_param] + (c[param2] - c[hill_param]) * q / (1 + q),
+ *                     q = (x_s / c[param3])^order, order in 1..8
+ *                     (the DNA switching rates F, G of Eq. (10), Sec. IV B)
+ * PARREP_PARAM:       a parameter c[hill_param] that multiplies the rate constant
+ *                     (e.g. gamma * b of Table IV)                                  */
+enum { PARREP_FALLING = 0, PARREP_HILL_REP = 1, PARREP_HILL_SWITCH = 2, PARREP_PARAM = 3 };
 
 /* Threshold units for decorrelation and dephasing: PARREP_STEPS counts
  * transitions (the paper's n_c, n_p); PARREP_TIME uses simulated time. */
@@ -99,11 +105,14 @@ typedef struct parrep_plan parrep_plan;
 typedef struct parrep_server parrep_server;
 
 typedef struct {
-    int32_t kind;        /* PARREP_FALLING or PARREP_HILL_REP                      */
-    int32_t species;     /* species index the factor reads                          */
-    int32_t order;       /* falling-factorial order (0..8)                          */
-    int32_t hill_param;  /* Hill only: index of the exponent in c                   */
-    double K;            /* Hill only: scale (> 0)                                   */
+    int32_t kind;        /* PARREP_FALLING, _HILL_REP, _HILL_SWITCH or _PARAM       */
+    int32_t species;     /* species index the factor reads (not PARAM)             */
+    int32_t order;       /* FALLING: order 0..8; HILL_SWITCH: exponent 1..8         */
+    int32_t hill_param;  /* HILL_REP: exponent; HILL_SWITCH: value at x_s = 0;
+                            PARAM: the parameter (indices into c)                   */
+    int32_t param2;      /* HILL_SWITCH: index of the value as x_s -> infinity      */
+    int32_t param3;      /* HILL_SWITCH: index of the scale (c[param3] > 0)         */
+    double K;            /* HILL_REP: scale (> 0)                                    */
 } parrep_factor;
 
 typedef struct {
@@ -179,10 +188,11 @@ const char* parrep_last_error(void);
 
 /* Define a reaction network (Sec. I A): n_species <= 4, n_reactions <= 8,
  * n_params <= 8, reactions rx[n_reactions] read during the call (host).
- * EINVAL when an index is out of range, an order exceeds 8, K <= 0, kappa
- * is negative or not finite, or a stoichiometric coefficient is outside
- * [-128, 127].  Solves need integral Hill exponents in [0, 64]
- * (EUNSUPPORTED otherwise). */
+ * EINVAL when an index is out of range, an order exceeds 8 (or a switch
+ * exponent is outside 1..8), K <= 0, kappa is negative or not finite, or a
+ * stoichiometric coefficient is outside [-128, 127].  Solves need integral
+ * Hill exponents in [0, 64] (EUNSUPPORTED otherwise) and positive switch
+ * scales c[param3] (EINVAL). */
 int parrep_net_create(parrep_ctx* ctx, int32_t n_species, int32_t n_reactions, int32_t n_params,
                       const parrep_reaction* rx, parrep_net** out);
 void parrep_net_destroy(parrep_net* net);

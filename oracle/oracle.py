@@ -26,7 +26,8 @@ COUNTER_NAMES = ("ev_decorr", "ev_dephase", "ev_par_credited", "ev_par_discarded
 
 class Factor(C.Structure):
     _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("order", C.c_int32),
-                ("hill_param", C.c_int32), ("K", C.c_double)]
+                ("hill_param", C.c_int32), ("param2", C.c_int32), ("param3", C.c_int32),
+                ("K", C.c_double)]
 
 
 class Reaction(C.Structure):
@@ -112,6 +113,8 @@ def make_net(net) -> Net:
             rx.f[k].species = f.species
             rx.f[k].order = f.order
             rx.f[k].hill_param = f.hill_param
+            rx.f[k].param2 = f.param2
+            rx.f[k].param3 = f.param3
             rx.f[k].K = f.K
     return s
 

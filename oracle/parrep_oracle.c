@@ -105,16 +105,28 @@ static double factor_value(const or_factor* f, const int32_t* x, const double* c
         }
         return (double)p;
     }
+    if (f->kind == OR_HILL_SWITCH) {
+        /* c_lo + (c_hi - c_lo) q/(1+q), q = (x/c_K)^n: Eq. (10) of Sec. IV B */
+        double y = (double)xs / c[f->param3];
+        double q = hill_power(y, (double)f->order);
+        double s = q / (1.0 + q);
+        return c[f->hill_param] + (c[f->param2] - c[f->hill_param]) * s;
+    }
     /* OR_HILL_REP: 1 / (1 + (x/K)^h) */
     double y = (double)xs / f->K;
     double q = hill_power(y, c[f->hill_param]);
     return 1.0 / (1.0 + q);
 }
 
+/* lambda = (c_rate kappa) * (PARAM factors) * (state factors), each group
+ * left to right. */
 static double propensity(const or_reaction* r, const int32_t* x, const double* c)
 {
     double lam = (r->rate_param >= 0) ? c[r->rate_param] * r->kappa : r->kappa;
-    for (int k = 0; k < r->n_factors; ++k) lam = lam * factor_value(&r->f[k], x, c);
+    for (int k = 0; k < r->n_factors; ++k)
+        if (r->f[k].kind == OR_PARAM) lam = lam * c[r->f[k].hill_param];
+    for (int k = 0; k < r->n_factors; ++k)
+        if (r->f[k].kind != OR_PARAM) lam = lam * factor_value(&r->f[k], x, c);
     return lam;
 }
 
@@ -170,11 +182,26 @@ static void grad_log_lambda(const or_reaction* r, const int32_t* x, const double
     if (r->rate_param >= 0) g[r->rate_param] += 1.0 / c[r->rate_param];
     for (int k = 0; k < r->n_factors; ++k) {
         const or_factor* f = &r->f[k];
-        if (f->kind != OR_HILL_REP) continue;
-        double y = (double)x[f->species] / f->K;
-        if (!(y > 0.0)) continue;             /* q ln y -> 0 as y -> 0 */
-        double q = hill_power(y, c[f->hill_param]);
-        g[f->hill_param] += -q * log(y) / (1.0 + q);
+        if (f->kind == OR_PARAM) {
+            g[f->hill_param] += 1.0 / c[f->hill_param];
+        } else if (f->kind == OR_HILL_SWITCH) {
+            /* phi = lo + (hi - lo) s, s = q/(1+q): d phi/d lo = 1 - s,
+             * d phi/d hi = s, d phi/d K = -(hi - lo) n s (1 - s) / K */
+            double phi = factor_value(f, x, c);
+            if (!(phi > 0.0)) continue;
+            double y = (double)x[f->species] / c[f->param3];
+            double q = hill_power(y, (double)f->order);
+            double s = q / (1.0 + q);
+            double lo = c[f->hill_param], hi = c[f->param2], K = c[f->param3];
+            g[f->hill_param] += (1.0 - s) / phi;
+            g[f->param2] += s / phi;
+            g[f->param3] += -(hi - lo) * f->order * s * (1.0 - s) / (K * phi);
+        } else if (f->kind == OR_HILL_REP) {
+            double y = (double)x[f->species] / f->K;
+            if (!(y > 0.0)) continue;             /* q ln y -> 0 as y -> 0 */
+            double q = hill_power(y, c[f->hill_param]);
+            g[f->hill_param] += -q * log(y) / (1.0 + q);
+        }
     }
 }
 

@@ -31,7 +31,7 @@ extern "C" {
 #define OR_NCOUNTERS 12
 #define OR_CYCLE_REC 12
 
-enum { OR_FALLING = 0, OR_HILL_REP = 1 };
+enum { OR_FALLING = 0, OR_HILL_REP = 1, OR_HILL_SWITCH = 2, OR_PARAM = 3 };
 enum { OR_STEPS = 0, OR_TIME = 1 };
 enum { OR_TAG_DECORR = 1, OR_TAG_DEPHASE = 2, OR_TAG_FV = 3, OR_TAG_PARALLEL = 4 };
 
@@ -51,10 +51,12 @@ enum {
 };
 
 typedef struct {
-    int32_t kind;        /* OR_FALLING or OR_HILL_REP */
+    int32_t kind;        /* OR_FALLING, OR_HILL_REP, OR_HILL_SWITCH or OR_PARAM */
     int32_t species;
-    int32_t order;       /* falling factorial order */
-    int32_t hill_param;  /* index of the Hill exponent in c */
+    int32_t order;       /* falling factorial order; switch exponent */
+    int32_t hill_param;  /* Hill exponent; switch value at 0; the PARAM parameter */
+    int32_t param2;      /* switch value at infinity */
+    int32_t param3;      /* switch scale */
     double K;            /* Hill scale */
 } or_factor;
 

@@ -36,7 +36,8 @@ class ParrepError(RuntimeError):
 
 class Factor(C.Structure):
     _fields_ = [("kind", C.c_int32), ("species", C.c_int32), ("order", C.c_int32),
-                ("hill_param", C.c_int32), ("K", C.c_double)]
+                ("hill_param", C.c_int32), ("param2", C.c_int32), ("param3", C.c_int32),
+                ("K", C.c_double)]
 
 
 class Reaction(C.Structure):
@@ -183,6 +184,8 @@ class Context:
                 rx[j].factor[k].species = f.species
                 rx[j].factor[k].order = f.order
                 rx[j].factor[k].hill_param = f.hill_param
+                rx[j].factor[k].param2 = f.param2
+                rx[j].factor[k].param3 = f.param3
                 rx[j].factor[k].K = f.K
         h = C.c_void_p()
         _check(lib().parrep_net_create(self.h, net.n_species, net.n_reactions, net.n_params, rx,

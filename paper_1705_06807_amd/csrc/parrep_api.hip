@@ -50,6 +50,10 @@ int validate_problem(const parrep_net* net, const parrep_problem* p, int64_t* nb
                 const double h = p->c[N.rx[j].f[f].hill_param];
                 if (!(h <= 64.0) || h != std::floor(h))
                     return fail(PARREP_EUNSUPPORTED, "Hill exponents must be integers in [0, 64]");
+            } else if (N.rx[j].f[f].kind == PARREP_HILL_SWITCH) {
+                const double K = p->c[N.rx[j].f[f].param3];
+                if (!(K > 0.0) || !std::isfinite(K))
+                    return fail(PARREP_EINVAL, "switch scales must be positive");
             }
     if (!(p->T > 0.0) || !(p->T < 0x1.0p51))
         return fail(PARREP_EINVAL, "T must be in (0, 2^51)");
@@ -108,16 +112,19 @@ void fill_inst(DevInst& d, const parrep_net* net, const parrep_problem* p, int64
     d.instance_id = p->instance_id;
     d.max_events = p->max_events;
     // Hot-path view: reactions with one state-dependent factor read a table
-    // of lambda_j over 0..tab_L-1 of that species.
+    // of lambda_j over 0..tab_L-1 of that species (parameter factors are part
+    // of the rate constant); two state factors take the formula.
     for (int j = 0; j < kMaxM; ++j) {
         const DevReaction& r = d.net.rx[j];
         uint32_t kind = kRxConst, sp = 0;
-        if (j < d.net.n_reactions && r.n_factors == 1) {
-            kind = kRxTable;
-            sp = (uint32_t)r.f[0].species;
-        } else if (j < d.net.n_reactions && r.n_factors > 1) {
-            kind = kRxDirect;
+        int nstate = 0;
+        for (int f = 0; j < d.net.n_reactions && f < r.n_factors; ++f) {
+            if (r.f[f].kind == PARREP_PARAM) continue;
+            if (nstate == 0) sp = (uint32_t)r.f[f].species;
+            ++nstate;
         }
+        if (nstate == 1) kind = kRxTable;
+        else if (nstate > 1) kind = kRxDirect;
         d.jmeta[j] = kind | (sp << 2);
         uint32_t packed = 0;
         for (int i = 0; i < kMaxS; ++i) packed |= ((uint32_t)(r.stoich[i] & 0xFF)) << (8 * i);
@@ -457,7 +464,13 @@ int parrep_net_create(parrep_ctx* ctx, int32_t n_species, int32_t n_reactions, i
         for (int f = 0; f < r.n_factors; ++f) {
             const parrep_factor& q = r.factor[f];
             bool ok = q.species >= 0 && q.species < n_species;
+            auto par = [&](int32_t i) { return i >= 0 && i < n_params; };
             if (q.kind == PARREP_FALLING) ok = ok && q.order >= 0 && q.order <= 8;
+            else if (q.kind == PARREP_HILL_SWITCH)
+                ok = ok && q.order >= 1 && q.order <= 8 && par(q.hill_param) && par(q.param2) &&
+                     par(q.param3);
+            else if (q.kind == PARREP_PARAM)
+                ok = par(q.hill_param);
             else if (q.kind == PARREP_HILL_REP)
                 ok = ok && q.hill_param >= 0 && q.hill_param < n_params && std::isfinite(q.K) &&
                      q.K > 0.0;
@@ -467,9 +480,11 @@ int parrep_net_create(parrep_ctx* ctx, int32_t n_species, int32_t n_reactions, i
                 return fail(PARREP_EINVAL, "reaction " + std::to_string(j) + ": bad factor");
             }
             d.f[f].kind = q.kind;
-            d.f[f].species = q.species;
-            d.f[f].order = q.kind == PARREP_FALLING ? q.order : 0;
-            d.f[f].hill_param = q.kind == PARREP_HILL_REP ? q.hill_param : 0;
+            d.f[f].species = q.kind == PARREP_PARAM ? 0 : q.species;
+            d.f[f].order = (q.kind == PARREP_FALLING || q.kind == PARREP_HILL_SWITCH) ? q.order : 0;
+            d.f[f].hill_param = q.kind == PARREP_FALLING ? 0 : q.hill_param;
+            d.f[f].param2 = q.kind == PARREP_HILL_SWITCH ? q.param2 : 0;
+            d.f[f].param3 = q.kind == PARREP_HILL_SWITCH ? q.param3 : 0;
             d.f[f].K = q.kind == PARREP_HILL_REP ? q.K : 1.0;
         }
     }

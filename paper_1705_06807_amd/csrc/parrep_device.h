@@ -184,7 +184,7 @@ struct SNet {
     int32_t m, n, np, R;
     int32_t nf[kMaxM];
     int32_t fkind[kMaxM][kMaxF], fsp[kMaxM][kMaxF], ford[kMaxM][kMaxF];
-    int32_t fhint[kMaxM][kMaxF], fhp[kMaxM][kMaxF];
+    int32_t fhint[kMaxM][kMaxF], fhp[kMaxM][kMaxF], fp2[kMaxM][kMaxF], fp3[kMaxM][kMaxF];
     int32_t rate_param[kMaxM];
     int32_t stoich[kMaxM][kMaxS];
     int32_t rw[kMaxS];
@@ -226,17 +226,23 @@ __device__ void load_net(SNet& S, const DevInst* I) {
         S.nf[j] = on ? rx.n_factors : 0;
         S.rate_param[j] = rx.rate_param;
         S.kappa[j] = rx.kappa;
-        S.k[j] = rx.rate_param >= 0 ? I->c[rx.rate_param] * rx.kappa : rx.kappa;
+        // k_j = c_rate kappa, then the parameter factors left to right
+        double kj = rx.rate_param >= 0 ? I->c[rx.rate_param] * rx.kappa : rx.kappa;
+        for (int f = 0; on && f < rx.n_factors; ++f)
+            if (rx.f[f].kind == PARREP_PARAM) kj = kj * I->c[rx.f[f].hill_param];
+        S.k[j] = kj;
         for (int i = 0; i < kMaxS; ++i) S.stoich[j][i] = rx.stoich[i];
         for (int f = 0; f < kMaxF; ++f) {
             S.fkind[j][f] = rx.f[f].kind;
             S.fsp[j][f] = rx.f[f].species;
             S.ford[j][f] = rx.f[f].order;
             S.fhp[j][f] = rx.f[f].hill_param;
+            S.fp2[j][f] = rx.f[f].param2;
+            S.fp3[j][f] = rx.f[f].param3;
             S.fK[j][f] = rx.f[f].K;
             S.fhint[j][f] = (rx.f[f].kind == PARREP_HILL_REP && f < S.nf[j])
                                 ? small_int_exponent(I->c[rx.f[f].hill_param])
-                                : 0;
+                                : (rx.f[f].kind == PARREP_HILL_SWITCH ? rx.f[f].order : 0);
         }
     }
 }
@@ -269,8 +275,21 @@ __device__ __forceinline__ double falling(int64_t xs, int order) {
 }
 
 // phi of factor f of reaction j at species value xs (main path: exponents from c).
+// phi of a switch factor: lo + (hi - lo) q/(1+q), q = (x/K)^n (repeated
+// multiplication), with lo, hi, K from cv.
+__device__ __forceinline__ double switch_val(int xs, int n, double lo, double hi, double K) {
+    const double y = (double)xs / K;
+    double q = y;
+    for (int i = 1; i < n; ++i) q = q * y;
+    const double s = q / (1.0 + q);
+    return lo + (hi - lo) * s;
+}
+
 __device__ __forceinline__ double factor_val(const SNet& S, int j, int f, int xs) {
     if (S.fkind[j][f] == PARREP_FALLING) return falling(xs, S.ford[j][f]);
+    if (S.fkind[j][f] == PARREP_HILL_SWITCH)
+        return switch_val(xs, S.ford[j][f], S.c[S.fhp[j][f]], S.c[S.fp2[j][f]],
+                          S.c[S.fp3[j][f]]);
     const double y = (double)xs / S.fK[j][f];
     const double q = hill_pow(y, S.fhint[j][f], S.c[S.fhp[j][f]]);
     return 1.0 / (1.0 + q);
@@ -281,11 +300,17 @@ template <int NS>
 __device__ double prop_with(const SNet& S, int j, const int (&x)[NS], const double* cv) {
     const int rp = S.rate_param[j];
     double lam = rp >= 0 ? cv[rp] * S.kappa[j] : S.kappa[j];
+    for (int f = 0; f < S.nf[j]; ++f)
+        if (S.fkind[j][f] == PARREP_PARAM) lam = lam * cv[S.fhp[j][f]];
     for (int f = 0; f < S.nf[j]; ++f) {
+        const int kind = S.fkind[j][f];
+        if (kind == PARREP_PARAM) continue;
         const int xs = pick<NS>(x, S.fsp[j][f]);
         double phi;
-        if (S.fkind[j][f] == PARREP_FALLING) {
+        if (kind == PARREP_FALLING) {
             phi = falling(xs, S.ford[j][f]);
+        } else if (kind == PARREP_HILL_SWITCH) {
+            phi = switch_val(xs, S.ford[j][f], cv[S.fhp[j][f]], cv[S.fp2[j][f]], cv[S.fp3[j][f]]);
         } else {
             const double h = cv[S.fhp[j][f]];
             const double y = (double)xs / S.fK[j][f];
@@ -317,14 +342,17 @@ __device__ __forceinline__ void apply_dx(int (&x)[NS], uint32_t dxp) {
 template <int NS>
 __device__ __forceinline__ double lambda_formula(const DevInst* __restrict__ I, int j,
                                                  const int (&x)[NS]) {
-    double lam = I->k[j];
+    double lam = I->k[j];  // includes the parameter factors
     const int nf = I->net.rx[j].n_factors;
     for (int f = 0; f < nf; ++f) {
         const DevFactor& fc = I->net.rx[j].f[f];
+        if (fc.kind == PARREP_PARAM) continue;
         const int xs = pick<NS>(x, fc.species);
         double phi;
         if (fc.kind == PARREP_FALLING) {
             phi = falling(xs, fc.order);
+        } else if (fc.kind == PARREP_HILL_SWITCH) {
+            phi = switch_val(xs, fc.order, I->c[fc.hill_param], I->c[fc.param2], I->c[fc.param3]);
         } else {
             const double y = (double)xs / fc.K;
             const int h = I->hexp[j * kMaxF + f];
@@ -636,15 +664,42 @@ __device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, WinAc
         for (int p = 0; p < kMaxP; ++p)
             if (p == rp) g[p] += 1.0 / S.c[rp];
         for (int f = 0; f < S.nf[j]; ++f) {
-            if (S.fkind[j][f] != PARREP_HILL_REP) continue;
-            const double y = (double)pick<NS>(x, S.fsp[j][f]) / S.fK[j][f];
-            if (!(y > 0.0)) continue;
+            const int kind = S.fkind[j][f];
             const int hp = S.fhp[j][f];
-            const double q = hill_pow(y, S.fhint[j][f], S.c[hp]);
-            const double d = -q * log(y) / (1.0 + q);
+            if (kind == PARREP_PARAM) {
+                const double d = 1.0 / S.c[hp];
 #pragma unroll
-            for (int p = 0; p < kMaxP; ++p)
-                if (p == hp) g[p] += d;
+                for (int p = 0; p < kMaxP; ++p)
+                    if (p == hp) g[p] += d;
+            } else if (kind == PARREP_HILL_SWITCH) {
+                // phi = lo + (hi - lo) s: d/dlo = 1 - s, d/dhi = s,
+                // d/dK = -(hi - lo) n s (1 - s) / K, each over phi
+                const int xs = pick<NS>(x, S.fsp[j][f]);
+                const int p2 = S.fp2[j][f], p3 = S.fp3[j][f], n = S.ford[j][f];
+                const double lo = S.c[hp], hi = S.c[p2], K = S.c[p3];
+                const double phi = switch_val(xs, n, lo, hi, K);
+                if (!(phi > 0.0)) continue;
+                const double y = (double)xs / K;
+                double q = y;
+                for (int i = 1; i < n; ++i) q = q * y;
+                const double s = q / (1.0 + q);
+                const double dlo = (1.0 - s) / phi, dhi = s / phi;
+                const double dK = -(hi - lo) * n * s * (1.0 - s) / (K * phi);
+#pragma unroll
+                for (int p = 0; p < kMaxP; ++p) {
+                    if (p == hp) g[p] += dlo;
+                    if (p == p2) g[p] += dhi;
+                    if (p == p3) g[p] += dK;
+                }
+            } else if (kind == PARREP_HILL_REP) {
+                const double y = (double)pick<NS>(x, S.fsp[j][f]) / S.fK[j][f];
+                if (!(y > 0.0)) continue;
+                const double q = hill_pow(y, S.fhint[j][f], S.c[hp]);
+                const double d = -q * log(y) / (1.0 + q);
+#pragma unroll
+                for (int p = 0; p < kMaxP; ++p)
+                    if (p == hp) g[p] += d;
+            }
         }
 #pragma unroll
         for (int a = 0; a < kMaxP; ++a)

@@ -18,7 +18,7 @@ constexpr int kMaxP = PARREP_MAX_PARAMS;
 enum : uint32_t { kTagDecorr = 1, kTagDephase = 2, kTagFV = 3, kTagParallel = 4 };
 
 struct DevFactor {
-    int32_t kind, species, order, hill_param;
+    int32_t kind, species, order, hill_param, param2, param3;
     double K;
 };
 
@@ -72,7 +72,7 @@ struct DevInst {
     double k[kMaxM];          // k_j = c[rate_param] * kappa (kappa when rate_param < 0)
     uint32_t jmeta[kMaxM];    // bits 0-1 kind (0 constant, 1 table, 2 direct), 2-3 species
     uint32_t jstoich[kMaxM];  // eta_j packed as int8 per species (species i in bits 8i..8i+7)
-    int32_t hexp[kMaxM * kMaxF];  // integral Hill exponents (setup kernel)
+    int32_t hexp[kMaxM * kMaxF];  // integral exponents: HILL_REP from c, HILL_SWITCH order
     int32_t tab_L;            // table entries per reaction (states 0..tab_L-1)
     int32_t tab_owner;        // 1: this instance's setup block fills the table
     double* tab;              // kMaxM * tab_L propensities, shared by equal (network, c)

@@ -6,13 +6,16 @@ oracle's tests and the HIP path's tests can both draw their inputs from it.
 
 Networks are described in one factored form used throughout the project:
 
-    lambda_j(x, c) = k_j * phi_j1(x) * phi_j2(x) * ...      (left to right)
-    k_j = c[rate_param_j] * kappa_j     (k_j = kappa_j when rate_param_j < 0)
+    lambda_j(x, c) = k_j * phi_j1(x) * phi_j2(x) * ...      (state factors, left to right)
+    k_j = c[rate_param_j] * kappa_j * c[p_1] * ...           (PARAM factors, left to right)
 
-with two factor kinds:
+with the factor kinds
 
-* ``FALLING``  phi(x) = x_s (x_s - 1) ... (x_s - order + 1)   (mass action)
-* ``HILL_REP`` phi(x) = 1 / (1 + (x_s / K) ** c[hill_param])   (repression)
+* ``FALLING``     phi(x) = x_s (x_s - 1) ... (x_s - order + 1)   (mass action)
+* ``HILL_REP``    phi(x) = 1 / (1 + (x_s / K) ** c[hill_param])   (repression)
+* ``HILL_SWITCH`` phi(x) = c[lo] + (c[hi] - c[lo]) q / (1 + q), q = (x_s / c[Kp]) ** order,
+  with lo = hill_param, hi = param2, Kp = param3   (switching rates, Eq. (10))
+* ``PARAM``       a parameter c[hill_param] in the rate constant
 
 Stoichiometry rows are net changes (products minus reactants), which is what
 both model tables of the paper list (Sec. IV, Tables I and IV).
@@ -27,6 +30,8 @@ import numpy as np
 
 FALLING = 0
 HILL_REP = 1
+HILL_SWITCH = 2
+PARAM = 3
 
 STEPS = 0
 TIME = 1
@@ -41,9 +46,11 @@ MAX_PARAMS = 8
 class Factor:
     kind: int
     species: int
-    order: int = 0          # FALLING only
+    order: int = 0          # FALLING: order; HILL_SWITCH: exponent
     K: float = 1.0          # HILL_REP only: x_s is divided by K
-    hill_param: int = -1    # HILL_REP only: index of the exponent in c
+    hill_param: int = -1    # HILL_REP: exponent; HILL_SWITCH: value at 0; PARAM: the parameter
+    param2: int = -1        # HILL_SWITCH: value as x_s -> infinity
+    param3: int = -1        # HILL_SWITCH: scale
 
 
 @dataclasses.dataclass(frozen=True)
@@ -168,6 +175,60 @@ def toggle(omega: float) -> Network:
 
 
 TOGGLE_C = (3.0, 3.0, 2.0, 2.0)
+
+
+def genetic_switch() -> Network:
+    """Genetic switch with positive feedback (Sec. IV B, Table IV, Eq. (10)).
+
+    Species (DNA_in, DNA_act, mRNA, protein); parameters ordered
+    (a, b, gamma, k0_min, k0_max, k1_min, k1_max, D).  Reactions: mRNA
+    production a*DNA_act, mRNA decay gamma*x1, protein production gamma*b*x1,
+    protein decay x2, and the DNA switching reactions that Table IV leaves
+    out: inactive -> active at F(x2) and active -> inactive at G(x2) with
+    F = k0_min + (k0_max - k0_min) x2^2/(x2^2 + D^2),
+    G = k1_max + (k1_min - k1_max) x2^2/(x2^2 + D^2).
+    """
+    sw = lambda lo, hi: Factor(HILL_SWITCH, 3, order=2, hill_param=lo, param2=hi, param3=7)
+    return Network(
+        name="genetic_switch",
+        n_species=4,
+        n_params=8,
+        param_names=("a", "b", "gamma", "k0_min", "k0_max", "k1_min", "k1_max", "D"),
+        reactions=(
+            Reaction(0, 1.0, (Factor(FALLING, 1, order=1),), (0, 0, 1, 0)),
+            Reaction(2, 1.0, (Factor(FALLING, 2, order=1),), (0, 0, -1, 0)),
+            Reaction(2, 1.0, (Factor(FALLING, 2, order=1), Factor(PARAM, 0, hill_param=1)),
+                     (0, 0, 0, 1)),
+            Reaction(-1, 1.0, (Factor(FALLING, 3, order=1),), (0, 0, 0, -1)),
+            Reaction(-1, 1.0, (sw(3, 4), Factor(FALLING, 0, order=1)), (-1, 1, 0, 0)),
+            Reaction(-1, 1.0, (sw(6, 5), Factor(FALLING, 1, order=1)), (1, -1, 0, 0)),
+        ),
+    )
+
+
+def genetic_switch_c(V: float = 2400.0) -> tuple:
+    """Parameters of Sec. IV B at system size V = a b (2400 in the paper):
+    b = 22.5, gamma = 50, a = V/b, k_min = V/(100 b), k_max = V/b,
+    D = 1000 V/2400 (the rates and the feedback scale follow V, so smaller
+    V gives the same structure with faster switching)."""
+    b = 22.5
+    return (V / b, b, 50.0, V / (100.0 * b), V / b, V / (100.0 * b), V / b, 1000.0 * V / 2400.0)
+
+
+def genetic_switch_problem(seed: int = 0, instance_id: int = 0, V: float = 2400.0, R: int = 100,
+                           n_c: float = 2e4, n_p: float = 2e4, T: float = 2e6,
+                           mode: int = STEPS) -> Problem:
+    """W+ = {x2 < 511.2865 V/2400} (the horizontal line through the saddle),
+    start at the low stable point with inactive DNA, histogram box
+    [0,1]^2 x [0, 24 V/2400] x [0, 3000 V/2400]."""
+    f = V / 2400.0
+    return Problem(
+        net=genetic_switch(), c=genetic_switch_c(V), x0=(1, 0, 0, int(round(25.2628 * f))),
+        region_w=(0, 0, 0, 1), region_theta=int(math.floor(511.2865 * f)) + 1,
+        R=R, decorr_mode=mode, decorr=n_c, dephase_mode=mode, dephase=n_p,
+        T=T, t_burn=T / 2.0, hist_lo=(0, 0, 0, 0),
+        hist_hi=(1, 1, int(math.ceil(24 * f)), int(math.ceil(3000 * f))),
+        rer_eps=(0.01,) * 8, seed=seed, instance_id=instance_id)
 
 
 def pure_death(rate: float = 1.0) -> Network:
