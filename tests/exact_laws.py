@@ -244,3 +244,128 @@ def conditioned_law(PW: sp.csr_matrix, start: int, n: int) -> np.ndarray:
 
 def tv(p: np.ndarray, q: np.ndarray) -> float:
     return 0.5 * float(np.abs(np.asarray(p, dtype=float) - np.asarray(q, dtype=float)).sum())
+
+
+# ----------------------------------------------------------------------------
+# Genetic switch (Sec. IV B): xi in {0,1} active DNA, x1 mRNA, x2 protein
+# ----------------------------------------------------------------------------
+
+GS_STOICH = ((0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1), (1, 0, 0), (-1, 0, 0))
+
+
+def genetic_switch_rates(xi, x1, x2, c):
+    """Table IV propensities and the switching rates F (inactive -> active)
+    and G (active -> inactive) of Eq. (10); c = (a, b, gamma, k0min, k0max,
+    k1min, k1max, D).  Channel order: transcription, mRNA decay, translation,
+    protein decay, activation, deactivation."""
+    a, b, g, k0n, k0x, k1n, k1x, D = c
+    xi = np.asarray(xi, dtype=np.float64)
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    h = x2 ** 2 / (x2 ** 2 + D ** 2)
+    F = k0n + (k0x - k0n) * h
+    G = k1x - (k1x - k1n) * h
+    return np.stack([a * xi, g * x1, g * b * x1, x2, F * (1 - xi), G * xi])
+
+
+def genetic_switch_grad(xi, x1, x2, c):
+    """d lam_j / d c_k, shape (8, 6, S), differentiated by hand from
+    genetic_switch_rates."""
+    a, b, g, k0n, k0x, k1n, k1x, D = c
+    xi = np.asarray(xi, dtype=np.float64)
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    h = x2 ** 2 / (x2 ** 2 + D ** 2)
+    dh = -2.0 * x2 ** 2 * D / (x2 ** 2 + D ** 2) ** 2
+    d = np.zeros((8, 6, xi.size))
+    d[0, 0] = xi
+    d[1, 2] = g * x1
+    d[2, 1] = x1
+    d[2, 2] = b * x1
+    d[3, 4] = (1 - h) * (1 - xi)
+    d[4, 4] = h * (1 - xi)
+    d[7, 4] = (k0x - k0n) * dh * (1 - xi)
+    d[5, 5] = h * xi
+    d[6, 5] = (1 - h) * xi
+    d[7, 5] = -(k1x - k1n) * dh * xi
+    return d
+
+
+class SwitchLattice:
+    """States (xi, x1, x2) in {0,1} x [0,N1] x [0,N2], numbered with x2
+    slowest so that the generator is banded (bandwidth 2 (N1+1)); transitions
+    leaving the box are dropped."""
+
+    def __init__(self, N1: int, N2: int):
+        self.N1, self.N2 = N1, N2
+        self.n = 2 * (N1 + 1) * (N2 + 1)
+
+    def idx(self, xi, x1, x2):
+        return (np.asarray(x2) * 2 + xi) * (self.N1 + 1) + x1
+
+    def states(self):
+        x2, xi, x1 = np.meshgrid(np.arange(self.N2 + 1), np.arange(2), np.arange(self.N1 + 1),
+                                 indexing="ij")
+        return xi.ravel(), x1.ravel(), x2.ravel()
+
+
+def genetic_switch_generator(c, N1: int, N2: int):
+    L = SwitchLattice(N1, N2)
+    xi, x1, x2 = L.states()
+    lam = genetic_switch_rates(xi, x1, x2, c)
+    rows, cols, vals = [], [], []
+    for j, (ds, d1, d2) in enumerate(GS_STOICH):
+        s2, m2, p2 = xi + ds, x1 + d1, x2 + d2
+        ok = (s2 >= 0) & (s2 <= 1) & (m2 >= 0) & (m2 <= N1) & (p2 >= 0) & (p2 <= N2) & (lam[j] > 0)
+        rows.append(L.idx(xi[ok], x1[ok], x2[ok]))
+        cols.append(L.idx(s2[ok], m2[ok], p2[ok]))
+        vals.append(lam[j][ok])
+    Q = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(L.n, L.n)).tocsr()
+    Q = Q - sp.diags(np.asarray(Q.sum(axis=1)).ravel())
+    return L, Q.tocsr()
+
+
+def _pin_solve(M: sp.csr_matrix, rhs: np.ndarray, k: int) -> np.ndarray:
+    """Solve M z = rhs with equation k replaced by z_k = rhs_k (keeps the
+    band; natural ordering)."""
+    A = M.tolil()
+    A[k, :] = 0.0
+    A[k, k] = 1.0
+    return spla.spsolve(A.tocsc(), rhs, permc_spec="NATURAL")
+
+
+def genetic_switch_pi(c, N1: int, N2: int):
+    """Stationary law on the truncated lattice: pi Q = 0 with pi pinned at a
+    state of positive mass (inactive DNA, no mRNA, protein near the low
+    equilibrium), then normalised."""
+    L, Q = genetic_switch_generator(c, N1, N2)
+    k = int(L.idx(0, 0, min(N2, max(1, int(round(25.0 * c[7] / 1000.0))))))
+    e = np.zeros(L.n)
+    e[k] = 1.0
+    pi = np.clip(_pin_solve(Q.T.tocsr(), e, k), 0.0, None)
+    return L, Q, pi / pi.sum()
+
+
+def ctmc_iaf(L, Q: sp.csr_matrix, pi: np.ndarray, f: np.ndarray) -> float:
+    """Asymptotic variance lim Var(int_0^T f)/T = 2 pi((f - pi f) g), where
+    Q g = -(f - pi f) (Poisson equation; g is defined up to a constant,
+    which drops out since pi(f - pi f) = 0)."""
+    d = np.asarray(f, dtype=np.float64) - float(pi @ f)
+    k = int(np.argmax(pi))
+    rhs = -d.copy()
+    rhs[k] = 0.0
+    g = _pin_solve(Q, rhs, k)
+    return float(2.0 * pi @ (d * g))
+
+
+def genetic_switch_fim_integrand(xi, x1, x2, c):
+    """Per-state path-space FIM integrand sum_j (d lam_j)(d lam_j)^T / lam_j, (S, 8, 8)."""
+    lam = genetic_switch_rates(xi, x1, x2, c)
+    d = genetic_switch_grad(xi, x1, x2, c)
+    out = np.zeros((lam.shape[1], 8, 8))
+    for j in range(6):
+        l = lam[j]
+        w = np.where(l > 0, 1.0 / np.where(l > 0, l, 1.0), 0.0)
+        out += np.einsum("as,bs,s->sab", d[:, j], d[:, j], w)
+    return out
