@@ -80,7 +80,7 @@ def test_philox_blocks(B, oracle):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("name", ["schlogl", "toggle", "toggle_beta"])
+@pytest.mark.parametrize("name", ["schlogl", "toggle", "toggle_beta", "genetic_switch"])
 def test_ssa_events(B, oracle, name):
     rng = np.random.default_rng(1)
     if name == "schlogl":
@@ -91,6 +91,12 @@ def test_ssa_events(B, oracle, name):
         net, c = W.toggle(50.0), W.TOGGLE_C
         states = rng.integers(0, 450, size=(3000, 2))
         states[:3] = [[0, 0], [0, 9], [9, 0]]
+    elif name == "genetic_switch":
+        net, c = W.genetic_switch(), W.genetic_switch_c(2400.0)
+        xi = rng.integers(0, 2, size=3000)
+        states = np.stack([1 - xi, xi, rng.integers(0, 12, size=3000),
+                           rng.integers(0, 4000, size=3000)], axis=1)
+        states[:4, 2:] = [[0, 0], [0, 1], [1, 0], [0, 1000]]
     else:  # non-integral Hill exponents are outside the GPU path
         net, c = W.toggle(50.0), (3.0, 3.0, 2.5, 1.5)
         with pytest.raises(B.ParrepError, match="integers"):
@@ -238,3 +244,37 @@ def test_full_size_toggle_sampled(B, oracle):
         hs[0].cycle_log = None
         o.cycle_log = None
         assert_same(o, hs[0], what="full-size")
+
+
+def _gs(i, V=240.0, **kw):
+    # the genetic switch of Sec. IV B at system size V; at V = 240 the wells
+    # are left every ~10-50 time units, so short runs see many cycles
+    f = V / 2400.0
+    kw.setdefault("hist_hi", (1, 1, int(math.ceil(24 * f)) + 6, int(math.ceil(3000 * f))))
+    p = W.genetic_switch_problem(seed=21, instance_id=i, V=V, R=kw.pop("R", 8),
+                                 T=kw.pop("T", 2000.0), n_c=kw.pop("n_c", 500),
+                                 n_p=kw.pop("n_p", 500))
+    return p.replace(**kw)
+
+
+GS_CASES = [
+    ("v240_R8", lambda i: _gs(i)),
+    ("v240_R100", lambda i: _gs(i, R=100, T=400.0)),
+    ("v240_time", lambda i: _gs(i, decorr_mode=W.TIME, decorr=2.0, dephase_mode=W.TIME,
+                                dephase=1.5)),
+    ("v240_narrow_hist", lambda i: _gs(i, hist_lo=(0, 0, 1, 20), hist_hi=(1, 1, 3, 200))),
+    ("v2400_R100", lambda i: _gs(i, V=2400.0, R=100, T=1500.0, n_c=2e4, n_p=2e4)),
+    ("v2400_R100_short", lambda i: _gs(i, V=2400.0, R=100, T=5000.0, n_c=2e3, n_p=2e3)),
+]
+
+
+@pytest.mark.parametrize("case", GS_CASES, ids=[c[0] for c in GS_CASES])
+def test_genetic_switch_solve_parity(B, oracle, case):
+    name, make = case
+    for i in range(2):
+        p = make(i)
+        _flush("case gs_%s instance %d R=%d" % (name, i, p.R))
+        o = oracle.run(p, cycle_log_cap=4096)
+        g = _gpu_run(B, p)
+        assert o.counters["n_cycle_log"] <= 4096
+        assert_same(o, g, what="gs_%s/%d" % (name, i))
