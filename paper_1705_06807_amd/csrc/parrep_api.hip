@@ -111,28 +111,45 @@ void fill_inst(DevInst& d, const parrep_net* net, const parrep_problem* p, int64
     d.seed = p->seed;
     d.instance_id = p->instance_id;
     d.max_events = p->max_events;
-    // Hot-path view: reactions with one state-dependent factor read a table
-    // of lambda_j over 0..tab_L-1 of that species (parameter factors are part
-    // of the rate constant); two state factors take the formula.
+    // Hot-path view (kinds described with kRxConst..kRxFall): parameter
+    // factors are part of the rate constant; the first state factor indexes
+    // a table unless it is a falling factorial of order <= 2 (outside the
+    // narrow kernels), and a second state factor is taken as a tail when it
+    // is such a falling factorial; anything else takes the formula.
+    const bool narrow = narrow_kernel(n, d.net.n_reactions);
     for (int j = 0; j < kMaxM; ++j) {
         const DevReaction& r = d.net.rx[j];
-        uint32_t kind = kRxConst, sp = 0;
-        int nstate = 0;
-        for (int f = 0; j < d.net.n_reactions && f < r.n_factors; ++f) {
-            if (r.f[f].kind == PARREP_PARAM) continue;
-            if (nstate == 0) sp = (uint32_t)r.f[f].species;
-            ++nstate;
+        int st[kMaxF], nstate = 0;
+        for (int f = 0; j < d.net.n_reactions && f < r.n_factors; ++f)
+            if (r.f[f].kind != PARREP_PARAM) st[nstate++] = f;
+        auto small_fall = [&](int f) {
+            return r.f[f].kind == PARREP_FALLING && r.f[f].order >= 1 && r.f[f].order <= 2;
+        };
+        uint32_t meta = jmeta_pack(kRxConst, 0, 0, 0, 0);
+        if (nstate >= 1) {
+            const DevFactor& f0 = r.f[st[0]];
+            const bool tail = nstate == 2 && !narrow && small_fall(st[1]);
+            const uint32_t ts = tail ? (uint32_t)r.f[st[1]].species : 0u;
+            const uint32_t to = tail ? (uint32_t)r.f[st[1]].order : 0u;
+            if (nstate > 2 || (nstate == 2 && !tail))
+                meta = jmeta_pack(kRxDirect, 0, 0, 0, 0);
+            else if (!narrow && small_fall(st[0]))
+                meta = jmeta_pack(kRxFall, (uint32_t)f0.species, (uint32_t)f0.order, ts, to);
+            else
+                meta = jmeta_pack(kRxTable, (uint32_t)f0.species, 0, ts, to);
         }
-        if (nstate == 1) kind = kRxTable;
-        else if (nstate > 1) kind = kRxDirect;
-        d.jmeta[j] = kind | (sp << 2);
+        d.jmeta[j] = meta;
         uint32_t packed = 0;
         for (int i = 0; i < kMaxS; ++i) packed |= ((uint32_t)(r.stoich[i] & 0xFF)) << (8 * i);
         d.jstoich[j] = packed;
     }
-    int hi = 0;
-    for (int i = 0; i < n; ++i) hi = std::max(hi, std::max(p->hist_hi[i], p->x0[i]));
-    d.tab_L = std::min(8192, std::max(256, ((hi + 64 + 63) / 64) * 64));
+    // table states per species: the histogram box and the start, plus 64
+    d.tab_L = 64;
+    for (int i = 0; i < kMaxS; ++i) {
+        const int hi = i < n ? std::max(p->hist_hi[i], p->x0[i]) : 0;
+        d.tab_Lsp[i] = std::min(8192, std::max(64, ((hi + 64 + 63) / 64) * 64));
+        d.tab_L = std::max(d.tab_L, d.tab_Lsp[i]);
+    }
 }
 
 namespace {
@@ -223,9 +240,12 @@ int shape_bucket(int R) {
     return b;
 }
 
-LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m) {
+LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m, bool sparse) {
     const int nsc = ns <= 1 ? 1 : (ns <= 2 ? 2 : 4);
     const int mc = m <= 4 ? 4 : 8;
+    // A batch that leaves CUs idle is bound by the latency of one event:
+    // one replica per lane over several waves beats stacking replicas.
+    if (sparse && R > 64 && R <= 256) return LaunchShape{1, 4, nsc, mc};
     auto it = ctx->tuned.find(std::make_tuple(shape_bucket(R), nsc, mc));
     if (it != ctx->tuned.end()) {
         LaunchShape s{it->second.first, it->second.second, nsc, mc};
@@ -245,7 +265,7 @@ std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
             sh[i].ns = d.net.n_species <= 1 ? 1 : (d.net.n_species <= 2 ? 2 : 4);
             sh[i].m = d.net.n_reactions <= 4 ? 4 : 8;
         } else {
-            sh[i] = pick_shape(ctx, d.R, d.net.n_species, d.net.n_reactions);
+            sh[i] = pick_shape(ctx, d.R, d.net.n_species, d.net.n_reactions, n <= ctx->n_cu);
         }
     }
     auto key = [&](int i) { return std::make_tuple(sh[i].ns, sh[i].m, sh[i].rpl, sh[i].waves); };
@@ -267,9 +287,10 @@ std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
         groups.back().count += 1;
     }
     for (Group& g : groups) {
-        int max_L = 1;
-        for (int i = g.first; i < g.first + g.count; ++i) max_L = std::max(max_L, insts[i].tab_L);
-        g.tab_Ls = table_lds_states(g.shape, max_L);
+        int need = 0;
+        for (int i = g.first; i < g.first + g.count; ++i)
+            need = std::max(need, table_lds_need(insts[i], g.shape));
+        g.tab_lds = table_lds_doubles(g.shape, need);
     }
     if (order) *order = ord;
     return groups;
@@ -288,7 +309,7 @@ int enqueue_batch(parrep_ctx* ctx, DevInst* d, int n, const std::vector<Group>& 
     if (groups.size() == 1) {
         const Group& g = groups[0];
         e = launch_solve(d + g.first, g.count, g.shape, mode, hook_cycle, hook_max_rounds,
-                         g.tab_Ls, st);
+                         g.tab_lds, st);
     } else {
         // Fork: group 0 on st, the others on auxiliary streams; join into st.
         while (ctx->aux.size() + 1 < groups.size()) {
@@ -307,7 +328,7 @@ int enqueue_batch(parrep_ctx* ctx, DevInst* d, int n, const std::vector<Group>& 
             if (k > 0) e = hipStreamWaitEvent(s, fork, 0);
             if (e == hipSuccess)
                 e = launch_solve(d + g.first, g.count, g.shape, mode, hook_cycle,
-                                 hook_max_rounds, g.tab_Ls, s);
+                                 hook_max_rounds, g.tab_lds, s);
             if (e == hipSuccess && k > 0) {
                 e = hipEventCreateWithFlags(&joins[k - 1], hipEventDisableTiming);
                 if (e == hipSuccess) e = hipEventRecord(joins[k - 1], s);
@@ -402,6 +423,8 @@ int parrep_ctx_create(int device, parrep_ctx** out) {
     int prev = 0;
     e = hipGetDevice(&prev);
     if (e == hipSuccess) e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
+                                                   device);
     if (e == hipSuccess) e = hipMalloc(&c->logtab, sizeof(host_tab));
     if (e == hipSuccess) e = hipMemcpy(c->logtab, host_tab, sizeof(host_tab), hipMemcpyHostToDevice);
     if (e != hipSuccess && c->logtab) (void)hipFree(c->logtab);
@@ -569,7 +592,9 @@ int parrep_events(parrep_ctx* ctx, const parrep_net* net, const double* c_host, 
     if (rc) return rc;
     std::vector<DevInst> insts(1);
     fill_inst(insts[0], net, &p, nb);
-    insts[0].tab_L = 1024;  // the hook stages states below 512; the rest take the formula path
+    // the hook stages 4096 doubles of table in LDS; other states take the formula
+    for (int i = 0; i < kMaxS; ++i) insts[0].tab_Lsp[i] = 1024;
+    insts[0].tab_L = 1024;
     rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;

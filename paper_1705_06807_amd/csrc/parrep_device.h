@@ -321,6 +321,18 @@ __device__ double prop_with(const SNet& S, int j, const int (&x)[NS], const doub
     return lam;
 }
 
+// k_j phi_1(xs): the rate constant times the first state factor at value xs
+// (the first steps of prop_with, in its order).
+__device__ __forceinline__ double prop_first(const SNet& S, int j, int xs) {
+    const int rp = S.rate_param[j];
+    double lam = rp >= 0 ? S.c[rp] * S.kappa[j] : S.kappa[j];
+    for (int f = 0; f < S.nf[j]; ++f)
+        if (S.fkind[j][f] == PARREP_PARAM) lam = lam * S.c[S.fhp[j][f]];
+    for (int f = 0; f < S.nf[j]; ++f)
+        if (S.fkind[j][f] != PARREP_PARAM) return lam * factor_val(S, j, f, xs);
+    return lam;
+}
+
 // ---------------------------------------------------------------------------
 // Hot-path propensities: uniform per-instance data is read from the
 // descriptor (scalar loads); per-lane work is table lookups.
@@ -368,6 +380,84 @@ __device__ __forceinline__ double lambda_formula(const DevInst* __restrict__ I, 
     return lam;
 }
 
+// Where the propensity tables of one instance sit in LDS: reaction j's table
+// holds states 0..len[j]-1 of its species at ltab[off[j]].
+// Narrow kernels (kAll): every reaction has a table of the same length Ls
+// (const and padding ones filled with k_j and 0), at off[j] = j Ls, Ls the
+// row length cut to what the doubles given to the workgroup allow.
+// General kernels: only the table reactions, each with the states of its
+// species; when they do not all fit, the longest are cut to a common length
+// (bisection on that length).
+template <int M>
+struct TabLayout {
+    int off[M], len[M];
+    int Ls;  // narrow kernels: the common length
+};
+
+template <int M, bool kAll>
+__device__ __forceinline__ TabLayout<M> tab_layout(const DevInst* __restrict__ I, int avail) {
+    TabLayout<M> t;
+    if (kAll) {
+        const int L = I->tab_L;
+        t.Ls = L < avail / M ? L : avail / M;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            t.off[j] = j * t.Ls;
+            t.len[j] = t.Ls;
+        }
+        return t;
+    }
+    int need[M];
+    int top = 0;
+    const int m = I->net.n_reactions;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const uint32_t meta = j < m ? I->jmeta[j] : jmeta_pack(kRxConst, 0, 0, 0, 0);
+        need[j] = (meta & 3u) == kRxTable ? I->tab_Lsp[(meta >> 2) & 3u] : 0;
+        top = need[j] > top ? need[j] : top;
+    }
+    auto total_at = [&](int cap) {
+        int tot = 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) tot += need[j] < cap ? need[j] : cap;
+        return tot;
+    };
+    int cap = top;
+    if (total_at(cap) > avail) {
+        int lo = 0, hi = top;  // total_at(lo) <= avail < total_at(hi)
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (total_at(mid) <= avail) lo = mid;
+            else hi = mid;
+        }
+        cap = lo;
+    }
+    int o = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        t.off[j] = o;
+        t.len[j] = need[j] < cap ? need[j] : cap;
+        o += t.len[j];
+    }
+    t.Ls = 0;
+    return t;
+}
+
+// Stage the tables in LDS (all threads of the workgroup take part).
+template <int M, bool kAll>
+__device__ __forceinline__ void stage_tables(const DevInst* __restrict__ I, const TabLayout<M>& t,
+                                             double* ltab, int tid, int nthreads) {
+    const int L = I->tab_L;
+    const int m = I->net.n_reactions;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const uint32_t kind = j < m ? I->jmeta[j] & 3u : kRxConst;
+        const double cst = (j < m && kind == kRxConst) ? I->k[j] : 0.0;
+        for (int xs = tid; xs < t.len[j]; xs += nthreads)
+            ltab[t.off[j] + xs] = kind == kRxTable ? I->tab[j * L + xs] : cst;
+    }
+}
+
 // Uniform per-instance network data of the event loop, loaded once per
 // phase (scalar registers): rate constants, per-reaction kind and species,
 // packed stoichiometry, and the LDS propensity tables.  M >= n_reactions;
@@ -378,27 +468,42 @@ struct HotNet {
     uint32_t stoich[M];  // packed eta_j
     uint64_t spack;      // M == 4: eta_j (species 0-1 as int8) in bits 16j..16j+15
     uint32_t species;    // 2 bits per reaction: the species its table is indexed by
-    int Ls;              // states 0..Ls-1 of each reaction's species are in the LDS table
+    uint32_t kinds;      // 2 bits per reaction: kRxConst..kRxFall
+    uint64_t fmeta;      // 8 bits per reaction: first order, tail species, tail order
+    int off[M], len[M];  // general kernels: states 0..len[j]-1 of reaction j at ltab[off[j]]
+    int Ls;              // narrow kernels: states 0..Ls-1 of every reaction at ltab[j Ls]
+    double k[M];         // rate constants (0 for the padding)
     bool any_direct;     // some reaction needs the formula at every state
     int32_t w[kMaxS];    // metastable set: {x : w.x >= theta}
     int64_t theta;
 };
 
 template <int M>
-__device__ __forceinline__ HotNet<M> load_hot(const DevInst* __restrict__ I, int Ls) {
+__device__ __forceinline__ HotNet<M> load_hot(const DevInst* __restrict__ I,
+                                              const TabLayout<M>& t) {
     HotNet<M> h;
     const int m = I->net.n_reactions;
     h.any_direct = false;
-    uint32_t sp = 0;
+    uint32_t sp = 0, kinds = 0;
+    uint64_t fm = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const uint32_t meta = j < m ? I->jmeta[j] : (uint32_t)kRxConst;
+        const uint32_t meta = j < m ? I->jmeta[j] : jmeta_pack(kRxConst, 0, 0, 0, 0);
         h.stoich[j] = j < m ? ufl(I->jstoich[j]) : 0u;
         sp |= ((meta >> 2) & 3u) << (2 * j);
+        kinds |= (meta & 3u) << (2 * j);
+        fm |= (uint64_t)((meta >> 4) & 0x3Fu) << (8 * j);
         h.any_direct = h.any_direct || ((meta & 3u) == kRxDirect);
+        h.off[j] = ufl(t.off[j]);
+        h.len[j] = ufl(t.len[j]);
+        h.k[j] = j < m ? __longlong_as_double((long long)ufl64(
+                             (uint64_t)__double_as_longlong(I->k[j])))
+                       : 0.0;
     }
     h.species = ufl(sp);
-    h.Ls = ufl(Ls);
+    h.kinds = ufl(kinds);
+    h.fmeta = ufl64(fm);
+    h.Ls = ufl(t.Ls);
     uint64_t pk = 0;
 #pragma unroll
     for (int j = 0; j < M && j < 4; ++j) pk |= (uint64_t)(h.stoich[j] & 0xFFFFu) << (16 * j);
@@ -419,12 +524,59 @@ __device__ __forceinline__ int region_hot(const HotNet<M>& h, const int (&x)[NS]
     return d >= h.theta ? 1 : 0;
 }
 
+// x_s (order 1) or x_s (x_s - 1) (order 2) as a double: the falling
+// factorial of a count x_s >= 0, exact, 0 where it vanishes.
+__device__ __forceinline__ double fall12(int xs, uint32_t order) {
+    return (double)(order == 2u ? (int64_t)xs * (int64_t)(xs - 1) : (int64_t)xs);
+}
+
+// lambda_j(x) on the hot path of the general (not narrow) kernels, by the
+// reaction's kind: a constant, a table entry or an inline falling factorial,
+// times the tail; the formula for direct reactions and for table states the
+// LDS does not hold (divergent, rare).
+template <int NS, int M>
+__device__ __forceinline__ double lam_general(const HotNet<M>& h, const DevInst* __restrict__ I,
+                                              const double* __restrict__ ltab,
+                                              const int (&x)[NS], int j) {
+    const uint32_t kind = (h.kinds >> (2 * j)) & 3u;
+    if (kind == kRxConst) return h.k[j];
+    if (kind == kRxDirect) return lambda_formula<NS>(I, j, x);
+    const uint32_t fm = (uint32_t)(h.fmeta >> (8 * j)) & 0x3Fu;
+    const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
+    double lam;
+    if (kind == kRxFall) {
+        lam = h.k[j] * fall12(xs, fm & 3u);
+    } else if ((unsigned)xs < (unsigned)h.len[j]) {
+        lam = ltab[h.off[j] + xs];
+    } else {
+        return lambda_formula<NS>(I, j, x);
+    }
+    const uint32_t to = (fm >> 4) & 3u;
+    if (to != 0u) lam = lam * fall12(pick<NS>(x, (int)((fm >> 2) & 3u)), to);
+    return lam;
+}
+
+// lambda_j(x) in the narrow kernels off the fast path: the table when the
+// lane's state is inside every table, else the constant or the formula.
+template <int NS, int M>
+__device__ __forceinline__ double lam_narrow(const HotNet<M>& h, const DevInst* __restrict__ I,
+                                             const double* __restrict__ ltab,
+                                             const int (&x)[NS], int j, bool inr) {
+    const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxConst;
+    if (kind != kRxDirect && inr)
+        return ltab[j * h.Ls + pick<NS>(x, (int)((h.species >> (2 * j)) & 3u))];
+    if (kind == kRxConst) return I->k[j];
+    return lambda_formula<NS>(I, j, x);
+}
+
 // One Gillespie event at x (the "generate tau and J" step of Alg. 1):
 // tau = -log(u_open)/a0 (+inf when absorbing) and the packed change of
 // channel J = first j with u_sel*a0 < S_j, S_j the left-to-right partial
-// sums.  Propensities come from the LDS tables, which hold exactly what the
-// defining formula gives; states outside the tables (rare; checked once per
-// event for the whole wave) and two-factor reactions use the formula.
+// sums.  Every propensity equals the defining formula bit for bit (tables
+// hold formula values; inline factors repeat its operations).  Narrow
+// kernels read every reaction from a table and take the formula for the
+// whole wave when a lane's state is outside the tables (rare) or a reaction
+// is direct; the general kernels decide per reaction.
 template <int NS, int M>
 __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
                                                     const DevInst* __restrict__ I,
@@ -432,32 +584,33 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
                                                     const int (&x)[NS], double neglog_u_open,
                                                     double u_sel_v, double& tau, int& J,
                                                     uint32_t& dxp, double* a0_out = nullptr) {
-    bool inr = true;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) inr = inr && (unsigned)x[i] < (unsigned)h.Ls;
+    constexpr bool kNarrowK = narrow_kernel(NS, M);
     double cum[M];
     double s = 0.0;
-    if (__builtin_expect(__ballot(!inr) == 0ull && !h.any_direct, 1)) {
+    bool inr = true;
+    if (kNarrowK) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
-            const double lam = ltab[j * h.Ls + xs];
-            s = j == 0 ? lam : s + lam;  // 0 + lam_1 = lam_1 (lam_1 >= 0)
-            cum[j] = s;
+        for (int i = 0; i < NS; ++i) inr = inr && (unsigned)x[i] < (unsigned)h.Ls;
+        if (__builtin_expect(__ballot(!inr) == 0ull && !h.any_direct, 1)) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
+                const double lam = ltab[j * h.Ls + xs];
+                s = j == 0 ? lam : s + lam;  // 0 + lam_1 = lam_1 (lam_1 >= 0)
+                cum[j] = s;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double lam = lam_narrow<NS, M>(h, I, ltab, x, j, inr);
+                s = j == 0 ? lam : s + lam;
+                cum[j] = s;
+            }
         }
     } else {
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            double lam;
-            const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxConst;
-            if (kind != kRxDirect && inr) {
-                const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
-                lam = ltab[j * h.Ls + xs];
-            } else if (kind == kRxConst) {
-                lam = I->k[j];
-            } else {
-                lam = lambda_formula<NS>(I, j, x);
-            }
+            const double lam = lam_general<NS, M>(h, I, ltab, x, j);
             s = j == 0 ? lam : s + lam;
             cum[j] = s;
         }
@@ -473,7 +626,7 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
     const double t = u_sel_v * s;
     // With at most two species and four reactions every eta_j fits 16 bits
     // of one 64-bit scalar: J is found by counting and eta_J by a shift.
-    constexpr bool kNarrow = NS <= 2 && M == 4;
+    constexpr bool kNarrow = kNarrowK;
     int pj;
     uint32_t d;
     if (kNarrow) {
@@ -499,16 +652,8 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
         uint32_t pos = 0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            double lam;
-            const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxConst;
-            if (kind != kRxDirect && inr) {
-                const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
-                lam = ltab[j * h.Ls + xs];
-            } else if (kind == kRxConst) {
-                lam = I->k[j];
-            } else {
-                lam = lambda_formula<NS>(I, j, x);
-            }
+            const double lam = kNarrowK ? lam_narrow<NS, M>(h, I, ltab, x, j, inr)
+                                        : lam_general<NS, M>(h, I, ltab, x, j);
             if (lam > 0.0) pos |= 1u << j;
         }
         pj = 31 - __clz(pos);
@@ -1007,7 +1152,7 @@ template <int NS, int M, int RPL, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL>, 8)))
 k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
-           int64_t hook_max_rounds, int tab_Ls) {
+           int64_t hook_max_rounds, int tab_lds) {
     constexpr int B = 64 * WAVES;
     constexpr int E = RPL * WAVES;
     __shared__ RunState rs;
@@ -1026,20 +1171,14 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
     constexpr size_t kXbufBytes = xbuf_lds_bytes(RPL, WAVES, NS);
     constexpr int kXbufInts = (int)(kXbufBytes / 4);
     int32_t* xbuf = kXbufBytes ? dyn_lds : I->xbuf;
-    // Propensity tables: states 0..Ls-1 of each table reaction are copied into
-    // LDS after the exchange buffer (the launcher reserved M * tab_Ls doubles).
-    const int L = I->tab_L;
-    const int Ls = L < tab_Ls ? L : tab_Ls;
+    // Propensity tables, copied into LDS after the exchange buffer (the
+    // launcher reserved tab_lds doubles for them).
     double* ltab = reinterpret_cast<double*>(dyn_lds + ((kXbufInts + 1) & ~1));
-    for (int i = tid; i < M * Ls; i += B) {
-        const int j = i / Ls;
-        const int xs = i - j * Ls;
-        const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxDirect;
-        ltab[i] = kind == kRxTable ? I->tab[j * L + xs] : (kind == kRxConst ? I->k[j] : 0.0);
-    }
+    const TabLayout<M> tl = tab_layout<M, narrow_kernel(NS, M)>(I, tab_lds);
+    stage_tables<M, narrow_kernel(NS, M)>(I, tl, ltab, tid, B);
     __shared__ double lgt[kLogTabLen];
     for (int i = tid; i < kLogTabLen; i += B) lgt[i] = I->logtab[i];
-    const HotNet<M> hn = load_hot<M>(I, Ls);
+    const HotNet<M> hn = load_hot<M>(I, tl);
     const int64_t max_ev = I->max_events > 0 ? I->max_events : (int64_t(1) << 50);
     int par = 0;
 

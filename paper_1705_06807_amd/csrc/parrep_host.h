@@ -15,6 +15,7 @@
 
 struct parrep_ctx {
     int device = 0;
+    int n_cu = 256;  // compute units of the device
     std::mutex mu;
     double* logtab = nullptr;  // device copy of the -log(u) reduction table
     // Streams (default priority) on which the launch groups of a batch run
@@ -54,16 +55,17 @@ void place_arena(std::vector<DevInst>& insts, char* base, bool share_tables = tr
 
 // Replica-count bucket used by the autotune table.
 int shape_bucket(int R);
-// Launch shape for an instance: the autotuned one when there is one, else
-// the library's default for R.
-LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m);
+// Launch shape for an instance: in a sparse batch (no more instances than
+// the device has CUs) the latency shape; else the autotuned one when there
+// is one, else the library's default for R.
+LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m, bool sparse);
 
 // A batch after grouping: instances reordered so that each launch-shape
 // group is contiguous, each group's instances by decreasing expected work
 // (longest first, so the hardware's dispatch order fills the tail).
 struct Group {
     LaunchShape shape;
-    int first, count, tab_Ls;
+    int first, count, tab_lds;
 };
 std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
                                std::vector<int>* order, const LaunchShape* forced);

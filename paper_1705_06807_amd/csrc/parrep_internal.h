@@ -69,13 +69,14 @@ struct DevInst {
     int64_t* phase_clock;  // optional: ticks in S1, S2, S3, total
     // hot-path network view (jmeta/jstoich/tab_L filled on the host from the
     // network; k and the tables computed on the device by the setup kernel)
-    double k[kMaxM];          // k_j = c[rate_param] * kappa (kappa when rate_param < 0)
-    uint32_t jmeta[kMaxM];    // bits 0-1 kind (0 constant, 1 table, 2 direct), 2-3 species
+    double k[kMaxM];          // k_j = c[rate_param] * kappa * parameter factors
+    uint32_t jmeta[kMaxM];    // hot-path kind of reaction j, see jmeta_* below
     uint32_t jstoich[kMaxM];  // eta_j packed as int8 per species (species i in bits 8i..8i+7)
     int32_t hexp[kMaxM * kMaxF];  // integral exponents: HILL_REP from c, HILL_SWITCH order
-    int32_t tab_L;            // table entries per reaction (states 0..tab_L-1)
+    int32_t tab_Lsp[kMaxS];   // table states wanted per indexing species (0..tab_Lsp[s]-1)
+    int32_t tab_L;            // row length of tab (max of tab_Lsp)
     int32_t tab_owner;        // 1: this instance's setup block fills the table
-    double* tab;              // kMaxM * tab_L propensities, shared by equal (network, c)
+    double* tab;              // kMaxM * tab_L: row j holds the table of reaction j
     const double* logtab;     // kLogTabLen: reduction table of -log(u) (context-owned)
     // library scratch
     double* acc;         // kAccLen doubles: outside-box accumulators
@@ -107,8 +108,25 @@ constexpr size_t xbuf_lds_bytes(int rpl, int waves, int ns) {
 // Run modes of the instance kernel.
 enum : int32_t { kModeSolve = 0, kModeDephaseOnly = 1, kModeParallelOnly = 2 };
 
-// Hot-path reaction kinds (DevInst::jmeta bits 0-1).
-enum : uint32_t { kRxConst = 0, kRxTable = 1, kRxDirect = 2 };
+// Hot-path reaction kinds (DevInst::jmeta bits 0-1):
+//   const  lambda_j = k_j (no state factor; also the padding reactions)
+//   table  lambda_j = T_j[x_s] (T_j[x_s] = k_j * phi_1(x_s), the first state
+//          factor, computed by the defining formula), times the tail
+//   fall   lambda_j = k_j * x_s (order 1) or k_j * x_s (x_s - 1) (order 2),
+//          times the tail (no table)
+//   direct the defining formula at every event
+// The tail is an optional second state factor, a falling factorial of order
+// 1 or 2 multiplied last (the formula's own order of operations, so every
+// kind gives the formula's value bit for bit).  Kernels specialised for at
+// most 2 species and 4 reactions ("narrow") only see const/table without
+// tails; there every reaction, const included, reads a table.
+enum : uint32_t { kRxConst = 0, kRxTable = 1, kRxDirect = 2, kRxFall = 3 };
+// jmeta = kind | species << 2 | first order << 4 | tail species << 6 | tail order << 8
+__host__ __device__ constexpr uint32_t jmeta_pack(uint32_t kind, uint32_t sp, uint32_t o1,
+                                                  uint32_t ts, uint32_t to) {
+    return kind | (sp << 2) | (o1 << 4) | (ts << 6) | (to << 8);
+}
+__host__ __device__ constexpr bool narrow_kernel(int ns, int m) { return ns <= 2 && m <= 4; }
 
 struct LaunchShape {
     int rpl, waves, ns;
@@ -117,11 +135,14 @@ struct LaunchShape {
 
 // Launchers (parrep_kernels.hip).
 hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, int mode,
-                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_Ls,
+                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_lds,
                         hipStream_t stream);
-// States per reaction of propensity table the workgroup can stage in LDS for
-// this shape (beyond them the formula is evaluated).
-int table_lds_states(LaunchShape shape, int max_tab_L);
+// Doubles of propensity table an instance of this shape wants in LDS (every
+// table whole), and the doubles a workgroup of the shape can give them
+// (the kernel shortens the longest tables to fit; states beyond take the
+// formula).
+int table_lds_need(const DevInst& d, LaunchShape shape);
+int table_lds_doubles(LaunchShape shape, int max_need);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream);

@@ -6,10 +6,11 @@ namespace parrep {
 namespace dev {
 
 // ---------------------------------------------------------------------------
-// Setup: rate constants k_j = c[rate_param] * kappa of every instance, and the
-// propensity tables lambda_j(x_s), x_s = 0..tab_L-1, of each reaction whose
-// propensity depends on one species (computed by the defining formula, so a
-// table entry is bit-identical to evaluating the formula at that state).
+// Setup: rate constants k_j (c[rate_param] kappa times the parameter factors)
+// of every instance, and the tables T_j[x_s] = k_j phi_1(x_s), x_s =
+// 0..tab_L-1, of the table reactions (phi_1 the first state factor; the
+// formula's own first steps, so a table entry times the tail is
+// bit-identical to evaluating the formula at that state).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_setup(DevInst* __restrict__ insts) {
     __shared__ SNet S;
@@ -30,9 +31,7 @@ __global__ void __launch_bounds__(256) k_setup(DevInst* __restrict__ insts) {
         const int xs = idx - j * L;
         const uint32_t meta = I->jmeta[j];
         if ((meta & 3u) != kRxTable) continue;
-        int x[kMaxS] = {0, 0, 0, 0};
-        x[(meta >> 2) & 3u] = xs;
-        I->tab[idx] = prop_with<kMaxS>(S, j, x, S.c);
+        I->tab[idx] = prop_first(S, j, xs);
     }
 }
 
@@ -174,18 +173,12 @@ __global__ void __launch_bounds__(256) k_events(const DevInst* __restrict__ inst
                                                 const uint32_t* __restrict__ blocks, double* a0o,
                                                 double* tauo, int32_t* Jo) {
     __shared__ double ltab[kMaxM * kEventsHookLs];
-    const int L = inst->tab_L;
-    const int Ls = L < kEventsHookLs ? L : kEventsHookLs;
-    for (int t = threadIdx.x; t < kMaxM * Ls; t += blockDim.x) {
-        const int j = t / Ls;
-        const uint32_t kind = j < inst->net.n_reactions ? inst->jmeta[j] & 3u : (uint32_t)kRxDirect;
-        ltab[t] = kind == kRxTable ? inst->tab[j * L + (t - j * Ls)]
-                                   : (kind == kRxConst ? inst->k[j] : 0.0);
-    }
+    const TabLayout<kMaxM> tl = tab_layout<kMaxM, false>(inst, kMaxM * kEventsHookLs);
+    stage_tables<kMaxM, false>(inst, tl, ltab, threadIdx.x, blockDim.x);
     __shared__ double lgt[kLogTabLen];
     for (int t = threadIdx.x; t < kLogTabLen; t += blockDim.x) lgt[t] = inst->logtab[t];
     __syncthreads();
-    const HotNet<kMaxM> hn = load_hot<kMaxM>(inst, Ls);
+    const HotNet<kMaxM> hn = load_hot<kMaxM>(inst, tl);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int x[kMaxS];
@@ -231,13 +224,13 @@ PARREP_DECL(4, 1) PARREP_DECL(4, 4) PARREP_DECL(4, 16)
 #undef PARREP_DECL
 
 hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mode,
-                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_Ls,
+                        uint32_t hook_cycle, int64_t hook_max_rounds, int tab_lds,
                         hipStream_t stream) {
     if (!shape_supported(s)) return hipErrorInvalidValue;
 #define PARREP_GO(NSv, Wv)                                                                    \
     if (s.ns == NSv && s.waves == Wv)                                                         \
         return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.m, s.rpl, mode, hook_cycle,  \
-                                               hook_max_rounds, tab_Ls, stream);
+                                               hook_max_rounds, tab_lds, stream);
     PARREP_GO(1, 1) PARREP_GO(1, 4) PARREP_GO(1, 16)
     PARREP_GO(2, 1) PARREP_GO(2, 4) PARREP_GO(2, 16)
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
@@ -250,12 +243,20 @@ hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream) {
     return hipGetLastError();
 }
 
-int table_lds_states(LaunchShape s, int max_tab_L) {
+int table_lds_need(const DevInst& d, LaunchShape s) {
+    const int M = s.m <= 4 ? 4 : 8;
+    if (narrow_kernel(s.ns, s.m)) return M * d.tab_L;
+    int need = 0;
+    for (int j = 0; j < d.net.n_reactions; ++j)
+        if ((d.jmeta[j] & 3u) == kRxTable) need += d.tab_Lsp[(d.jmeta[j] >> 2) & 3u];
+    return need;
+}
+
+int table_lds_doubles(LaunchShape s, int max_need) {
     const size_t xb = xbuf_lds_bytes(s.rpl, s.waves, s.ns);
     const size_t budget = 56 * 1024;  // leaves room for the static LDS of the kernel
-    const int M = s.m <= 4 ? 4 : 8;
-    const size_t fit = xb < budget ? (budget - xb) / (8 * (size_t)M) : 0;
-    return (int)(fit < (size_t)max_tab_L ? fit : (size_t)max_tab_L);
+    const size_t fit = xb < budget ? (budget - xb) / 8 : 0;
+    return (int)(fit < (size_t)max_need ? fit : (size_t)max_need);
 }
 
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream) {

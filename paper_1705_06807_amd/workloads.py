@@ -220,14 +220,15 @@ def genetic_switch_problem(seed: int = 0, instance_id: int = 0, V: float = 2400.
                            mode: int = STEPS) -> Problem:
     """W+ = {x2 < 511.2865 V/2400} (the horizontal line through the saddle),
     start at the low stable point with inactive DNA, histogram box
-    [0,1]^2 x [0, 24 V/2400] x [0, 3000 V/2400]."""
+    [0,1]^2 x [0, 24 V/2400] x [0, 4000 V/2400] (at V = 2400 the stationary
+    law leaves about 3e-12 of its mass above 4000 proteins)."""
     f = V / 2400.0
     return Problem(
         net=genetic_switch(), c=genetic_switch_c(V), x0=(1, 0, 0, int(round(25.2628 * f))),
         region_w=(0, 0, 0, 1), region_theta=int(math.floor(511.2865 * f)) + 1,
         R=R, decorr_mode=mode, decorr=n_c, dephase_mode=mode, dephase=n_p,
         T=T, t_burn=T / 2.0, hist_lo=(0, 0, 0, 0),
-        hist_hi=(1, 1, int(math.ceil(24 * f)), int(math.ceil(3000 * f))),
+        hist_hi=(1, 1, int(math.ceil(24 * f)), int(math.ceil(4000 * f))),
         rer_eps=(0.01,) * 8, seed=seed, instance_id=instance_id)
 
 

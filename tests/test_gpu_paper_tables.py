@@ -111,3 +111,82 @@ def test_paper_schlogl_speedup_vs_replicas(B):
         print("R=%3d: speedup %.1f (cycles %d)" % (R, sp[R], c[4]), flush=True)
     assert sp[20] < sp[50] < sp[100]
     assert sp[100] > 10.0
+
+
+def _golden_gs():
+    g = {}
+    for line in open(os.path.join(HERE, "golden", "paper_genetic_switch_v2400.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v, hw = line.split()[:3]
+        g[k] = (float(v), None if hw == "-" else float(hw))
+    return g
+
+
+def test_paper_genetic_switch_tables(B):
+    """The genetic switch of Sec. IV B (V = 2400, W+ = {protein <= 511},
+    R = 100, n_c = n_p = 2e4 transitions, 100 trajectories) with the horizon
+    cut from the paper's 2e6 to 2e5 (burn-in T/2): the mean pathwise FIM
+    diagonal (Table V) within 4 half-widths of the exact stationary value of
+    the generator, and the IAFs (Table VI) of active DNA, mRNA and protein
+    from the spread of the window integrals."""
+    import torch
+    N, T = 100, 2e5
+    probs = [W.genetic_switch_problem(seed=0, instance_id=i, T=T) for i in range(N)]
+    print("paper genetic switch: %d trajectories, T=%g, n_c=n_p=2e4, R=100" % (N, T), flush=True)
+    outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+    torch.cuda.synchronize()
+    hs = [o.to_host() for o in outs]
+    assert [h.T_s for h in hs] == [T] * N
+    assert [h.counters["spill_overflow"] for h in hs] == [0] * N
+    fim = np.array([np.diag(h.fim) for h in hs])             # (N, 8)
+    m = fim.mean(axis=0)
+    hw = 1.96 * fim.std(axis=0, ddof=1) / math.sqrt(N)
+    y = np.array([h.y for h in hs])                          # window integrals, (N, 4)
+    iaf = ((y - y.mean(axis=0)) ** 2).sum(axis=0) / ((T - T / 2) * (N - 1))
+
+    c = W.genetic_switch_c(2400.0)
+    L, Q, pi = E.genetic_switch_pi(c, 14, 3300)
+    xi, x1, x2 = L.states()
+    fim_exact = np.diag(np.einsum("s,sab->ab", pi, E.genetic_switch_fim_integrand(xi, x1, x2, c)))
+    iaf_exact = [E.ctmc_iaf(L, Q, pi, f.astype(np.float64)) for f in (xi, x1, x2)]
+    g = _golden_gs()
+    print("%-8s %-24s %-12s %-s" % ("", "GPU (95% half-width)", "exact", "paper (T = 2e6)"))
+    for k in range(8):
+        pv, phw = g["fim_%d%d" % (k + 1, k + 1)]
+        print("FIM_%d%d   %11.5g +- %-10.3g %-12.5g %g +- %g" % (k + 1, k + 1, m[k], hw[k],
+                                                                fim_exact[k], pv, phw))
+    for name, k, ie in (("active", 1, iaf_exact[0]), ("mRNA", 2, iaf_exact[1]),
+                        ("protein", 3, iaf_exact[2])):
+        key = {"active": "iaf_active_dna", "mRNA": "iaf_mrna", "protein": "iaf_protein"}[name]
+        print("IAF %-8s %-22.4g %-12.4g %g" % (name, iaf[k], ie, g[key][0]))
+    print("IAF inactive %-18.4g (equals active: DNA_in = 1 - DNA_act)" % iaf[0], flush=True)
+
+    for k in range(8):
+        assert abs(m[k] - fim_exact[k]) < 4 * hw[k], k
+    # DNA_in + DNA_act = 1 on every trajectory, so their IAFs coincide
+    assert iaf[0] == pytest.approx(iaf[1], rel=1e-9)
+    # IAFs from N = 100 window integrals: relative standard error ~14 %
+    for k, ie in ((1, iaf_exact[0]), (2, iaf_exact[1]), (3, iaf_exact[2])):
+        assert abs(iaf[k] / ie - 1.0) < 0.45, (k, iaf[k], ie)
+
+
+def test_paper_genetic_switch_speedup_vs_replicas(B):
+    """Speedup (serial SSA steps over ParRep's on R ideal processors, as in
+    the Schloegl test) of the genetic switch at n_c = n_p = 2e4: the paper
+    reports about 7x at R = 100, less than for the Schloegl model because the
+    thresholds must be large."""
+    import torch
+    N, T = 20, 2e4
+    sp = {}
+    for R in (20, 50, 100):
+        probs = [W.genetic_switch_problem(seed=1, instance_id=i, R=R, T=T) for i in range(N)]
+        outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+        torch.cuda.synchronize()
+        c = np.array([o.counters.cpu().numpy() for o in outs]).sum(axis=0)
+        serial = c[0] + c[2]
+        parrep = c[0] + c[6] + c[5]
+        sp[R] = serial / parrep
+        print("R=%3d: speedup %.1f (cycles %d)" % (R, sp[R], c[4]), flush=True)
+    assert sp[20] < sp[50] < sp[100]
+    assert sp[100] > 3.0
