@@ -5,7 +5,7 @@ The oracle evaluates this network through its generic factored propensities
 rates F and G of Eq. (10) are two-level Hill factors).  The pins come from
 outside the oracle:
 
-* the equilibria of the rescaled RRE, Eq. (11), that the paper prints: the
+* the equilibria of the rescaled RRE, Eq. (12), that the paper prints: the
   oracle's own F and G (read off its propensities at integer protein counts)
   must bracket and, interpolated, reproduce them;
 * Table V: the stationary path-space FIM diagonal.  The exact value is
@@ -86,7 +86,7 @@ def test_oracle_switching_rates(oracle):
 
 
 def test_oracle_gives_the_papers_equilibria(oracle):
-    """Fixed points of Eq. (11): x2 = a b p(x2), x1 = x2 / (gamma b), with
+    """Fixed points of Eq. (12): x2 = a b p(x2), x1 = x2 / (gamma b), with
     p = F / (F + G).  F and G are taken from the oracle's activation and
     deactivation propensities at integer protein counts; the printed
     equilibria must lie between consecutive integers where x2 - a b p(x2)
