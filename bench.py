@@ -161,6 +161,7 @@ def forms(B, W, ctx, args):
     lat = np.array([i["latency_s"] for i in infos])
     runs = int(sum(i["runs"] for i in infos))
     met = sum(1 for i in infos if i["rse"] <= 0.02)
+    large = large_single_run(B, W, ctx) if not args.no_large else None
     return {
         "workload": "C3 mix (128 Schloegl c x logU[0.9,1.1], 128 toggle Omega~U{25..100}, "
                     "R~logU[64,4096]) and C5 stream (Schloegl / toggle Omega~U{25..150}, "
@@ -180,7 +181,28 @@ def forms(B, W, ctx, args):
             "rse_target": 0.02, "runs_per_request": [runs_min, runs_max],
             "met_target": met,
         },
+        "large_single_run": large,
     }
+
+
+def large_single_run(B, W, ctx):
+    """One solve of the large single run (toggle Omega = 150, R = 65536,
+    T = 1e5, histogram [0, 1200]^2): wall time and events/s of one instance,
+    which occupies one workgroup of 16 waves with 64 replicas per lane."""
+    import torch
+    p = W.c4_toggle(seed=0)
+    out = B.Outputs(ctx, p, cycle_log_cap=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.parrep_solve_batch([p], ctx=ctx, outputs=[out])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h = out.to_host()
+    ev = h.events
+    log("large single run: %.2f s, %.3g events/s" % (dt, ev / dt))
+    return {"workload": "toggle Omega=150, R=65536, t_c=t_p=20, T=1e5, hist [0,1200]^2, one instance",
+            "seconds": dt, "events": int(ev), "events_per_s": ev / dt,
+            "cycles": int(h.counters["cycles"]), "reached_T": h.T_s == p.T}
 
 
 def main():
@@ -201,6 +223,8 @@ def main():
                     help="skip the batched / served measurement")
     ap.add_argument("--forms-T", type=float, default=200.0)
     ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large single run (R = 65536) in the forms section")
     ap.add_argument("--phase-clock", action="store_true",
                     help="report where each trajectory's workgroup spent its time")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

@@ -39,7 +39,7 @@ extern "C" {
 #define PARREP_MAX_REACTIONS 8
 #define PARREP_MAX_FACTORS 2
 #define PARREP_MAX_PARAMS 8
-#define PARREP_MAX_REPLICAS 16384
+#define PARREP_MAX_REPLICAS 65536
 #define PARREP_NCOUNTERS 12
 #define PARREP_CYCLE_REC 12
 #define PARREP_NSTATS 80
@@ -169,7 +169,7 @@ typedef struct {
  * optional hipEvent_t handles (NULL = none) recorded on the stream right
  * before and right after the instance kernel, so a caller can time it. */
 typedef struct {
-    int32_t replicas_per_lane;  /* 1, 4 or 16                                        */
+    int32_t replicas_per_lane;  /* 1, 4 or 16; or 64 with 16 waves (R > 16384)       */
     int32_t waves;              /* 1, 4 or 16 (64-lane wavefronts per workgroup)      */
     void* event_before;         /* hipEvent_t or NULL                                 */
     void* event_after;          /* hipEvent_t or NULL                                 */

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libparrep.so")
 
 MAX_S, MAX_M, MAX_F, MAX_P = 4, 8, 2, 8
-MAX_REPLICAS = 16384
+MAX_REPLICAS = 65536
 NCOUNTERS = 12
 CYCLE_REC = 12
 NSTATS = 80

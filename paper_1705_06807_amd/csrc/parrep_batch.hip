@@ -196,10 +196,10 @@ int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem
     if (e != hipSuccess) return hip_fail(e, "autotune setup");
     float best = -1.0f;
     LaunchShape best_s{};
-    const int opts[3] = {1, 4, 16};
-    for (int a = 0; a < 3 && !rc; ++a)
+    const int ropts[4] = {1, 4, 16, 64}, wopts[3] = {1, 4, 16};
+    for (int a = 0; a < 4 && !rc; ++a)
         for (int b = 0; b < 3 && !rc; ++b) {
-            LaunchShape s{opts[a], opts[b], nsc, mc};
+            LaunchShape s{ropts[a], wopts[b], nsc, mc};
             const int64_t cap = (int64_t)s.rpl * s.waves * 64;
             if (cap < R || cap > 16 * (int64_t)std::max(R, 64) || !shape_supported(s)) continue;
             // all trial instances write the same (scratch) outputs: only the

@@ -28,6 +28,7 @@
 #include "parrep_neglog.h"
 
 #include <climits>
+#include <type_traits>
 
 namespace parrep {
 namespace dev {
@@ -532,15 +533,18 @@ __device__ __forceinline__ double fall12(int xs, uint32_t order) {
 
 // lambda_j(x) on the hot path of the general (not narrow) kernels, by the
 // reaction's kind: a constant, a table entry or an inline falling factorial,
-// times the tail; the formula for direct reactions and for table states the
-// LDS does not hold (divergent, rare).
+// times the tail.  Direct reactions, and table states the LDS does not hold,
+// set bit j of *need instead: the caller evaluates the formula for them in
+// one rolled loop (rare and divergent; one copy of the formula per event).
 template <int NS, int M>
-__device__ __forceinline__ double lam_general(const HotNet<M>& h, const DevInst* __restrict__ I,
-                                              const double* __restrict__ ltab,
-                                              const int (&x)[NS], int j) {
+__device__ __forceinline__ double lam_general(const HotNet<M>& h, const double* __restrict__ ltab,
+                                              const int (&x)[NS], int j, uint32_t* need) {
     const uint32_t kind = (h.kinds >> (2 * j)) & 3u;
     if (kind == kRxConst) return h.k[j];
-    if (kind == kRxDirect) return lambda_formula<NS>(I, j, x);
+    if (kind == kRxDirect) {
+        *need |= 1u << j;
+        return 0.0;
+    }
     const uint32_t fm = (uint32_t)(h.fmeta >> (8 * j)) & 0x3Fu;
     const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
     double lam;
@@ -549,11 +553,31 @@ __device__ __forceinline__ double lam_general(const HotNet<M>& h, const DevInst*
     } else if ((unsigned)xs < (unsigned)h.len[j]) {
         lam = ltab[h.off[j] + xs];
     } else {
-        return lambda_formula<NS>(I, j, x);
+        *need |= 1u << j;
+        return 0.0;
     }
     const uint32_t to = (fm >> 4) & 3u;
     if (to != 0u) lam = lam * fall12(pick<NS>(x, (int)((fm >> 2) & 3u)), to);
     return lam;
+}
+
+// All M propensities of the general kernels.
+template <int NS, int M>
+__device__ __forceinline__ void lams_general(const HotNet<M>& h, const DevInst* __restrict__ I,
+                                             const double* __restrict__ ltab,
+                                             const int (&x)[NS], double (&lam)[M]) {
+    uint32_t need = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) lam[j] = lam_general<NS, M>(h, ltab, x, j, &need);
+    if (need) {
+#pragma unroll 1
+        for (int j = 0; j < M; ++j) {
+            if (!((need >> j) & 1u)) continue;
+            const double v = lambda_formula<NS>(I, j, x);
+#pragma unroll
+            for (int jj = 0; jj < M; ++jj) lam[jj] = jj == j ? v : lam[jj];
+        }
+    }
 }
 
 // lambda_j(x) in the narrow kernels off the fast path: the table when the
@@ -608,10 +632,11 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
             }
         }
     } else {
+        double lam[M];
+        lams_general<NS, M>(h, I, ltab, x, lam);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const double lam = lam_general<NS, M>(h, I, ltab, x, j);
-            s = j == 0 ? lam : s + lam;
+            s = j == 0 ? lam[j] : s + lam[j];
             cum[j] = s;
         }
     }
@@ -650,12 +675,16 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
     }
     if (pj < 0) {  // only for non-finite a0: the last channel with lambda > 0
         uint32_t pos = 0;
+        double lam[M];
+        if (kNarrowK) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const double lam = kNarrowK ? lam_narrow<NS, M>(h, I, ltab, x, j, inr)
-                                        : lam_general<NS, M>(h, I, ltab, x, j);
-            if (lam > 0.0) pos |= 1u << j;
+            for (int j = 0; j < M; ++j) lam[j] = lam_narrow<NS, M>(h, I, ltab, x, j, inr);
+        } else {
+            lams_general<NS, M>(h, I, ltab, x, lam);
         }
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (lam[j] > 0.0) pos |= 1u << j;
         pj = 31 - __clz(pos);
         d = I->jstoich[pj];
     }
@@ -1155,6 +1184,11 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
            int64_t hook_max_rounds, int tab_lds) {
     constexpr int B = 64 * WAVES;
     constexpr int E = RPL * WAVES;
+    // Loops over a lane's replica slots are unrolled up to 16 slots (the
+    // per-slot state stays in registers); with 64 slots they stay rolled and
+    // the per-slot arrays live in the lane's private memory.
+    constexpr int kUK = RPL <= 16 ? RPL : 1;
+    using SlotMask = typename std::conditional<(RPL > 32), uint64_t, uint32_t>::type;
     __shared__ RunState rs;
     __shared__ Shared<E, WAVES> sh;
     extern __shared__ int32_t dyn_lds[];
@@ -1257,7 +1291,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         int64_t round2 = 0;
         if (mode != kModeParallelOnly) {
             double tr[RPL];
-#pragma unroll
+#pragma unroll kUK
             for (int k = 0; k < RPL; ++k) {
 #pragma unroll
                 for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
@@ -1277,9 +1311,9 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     break;
                 }
                 const int p = (int)(round2 & 1);
-                uint32_t exitbits = 0;
+                SlotMask exitbits = 0;
                 bool nd = false;
-#pragma unroll
+#pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
                     if (r < R) {
@@ -1291,7 +1325,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         ssa_event<NS, M>(hn, I, ltab, lgt, Y[k], b, tau, J, dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
-                        if (region_hot<NS, M>(hn, Y[k]) != W) exitbits |= 1u << k;
+                        if (region_hot<NS, M>(hn, Y[k]) != W) exitbits |= (SlotMask)1 << k;
                         if (!(tr[k] >= t_p)) nd = true;
                     }
                 }
@@ -1299,7 +1333,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 // replicas left W and whether one is still short of t_p.  The
                 // flags alternate between two slots, so the posts of round
                 // n+1 never meet a slow wave's reads of round n.
-                const bool wave_exit = __ballot(exitbits != 0u) != 0ull;
+                const bool wave_exit = __ballot(exitbits != 0) != 0ull;
                 const bool wave_nd = __ballot(nd) != 0ull;
                 if (lane == 0) sh.flags[p][wid] = (wave_nd ? 1 : 0) | (wave_exit ? 2 : 0);
                 __syncthreads();
@@ -1316,14 +1350,14 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     // that round's flag barrier, which every wave reaches after
                     // its reads here.
                     int32_t* xb = xbuf;
-#pragma unroll
+#pragma unroll kUK
                     for (int k = 0; k < RPL; ++k) {
                         const int r = k * B + tid;
                         if (r < R) {
 #pragma unroll
                             for (int i = 0; i < NS; ++i) xb[r * NS + i] = Y[k][i];
                         }
-                        const bool surv = (r < R) && !((exitbits >> k) & 1u);
+                        const bool surv = (r < R) && !((exitbits >> k) & 1);
                         const uint64_t m = __ballot(surv);
                         if (lane == 0) {
                             sh.mask[0][k * WAVES + wid] = m;
@@ -1335,9 +1369,9 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     for (int e = 0; e < E; ++e) nS += sh.cnt[0][e];
                     nS = ufl(nS);
                     if (exitbits) {
-#pragma unroll
+#pragma unroll kUK
                         for (int k = 0; k < RPL; ++k) {
-                            if (!((exitbits >> k) & 1u)) continue;
+                            if (!((exitbits >> k) & 1)) continue;
                             const int r = k * B + tid;
                             if (nS > 0) {
                                 const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagFV,
@@ -1387,7 +1421,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 break;
             }
             if (mode == kModeDephaseOnly) {
-#pragma unroll
+#pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
                     if (r < R) {
@@ -1400,7 +1434,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 return;
             }
         } else {
-#pragma unroll
+#pragma unroll kUK
             for (int k = 0; k < RPL; ++k) {
                 const int r = k * B + tid;
 #pragma unroll
@@ -1432,7 +1466,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             }
             Fx lsum{0, 0};
             int lfirst = INT_MAX;
-#pragma unroll
+#pragma unroll kUK
             for (int k = 0; k < RPL; ++k) {
                 const int r = k * B + tid;
                 tauk[k] = 0.0;
@@ -1460,7 +1494,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             const int K = ex ? first + 1 : R;
             if (ex) {
                 Fx l2{0, 0};
-#pragma unroll
+#pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
                     if (r < K) l2 = fx_add(l2, fx_from(tauk[k]));
@@ -1476,7 +1510,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             if (!boundary) {
                 if (accum) {
                     const bool win = fx_ge(C, tbq);
-#pragma unroll
+#pragma unroll kUK
                     for (int k = 0; k < RPL; ++k) {
                         const int r = k * B + tid;
                         if (r < K) add_credit<NS>(I, Y[k], tauk[k], win ? tauk[k] : 0.0);
@@ -1488,7 +1522,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 // Rare: an exact scan in key order finds where the burn-in
                 // time and the horizon fall.
                 uint64_t* sb = I->sbuf;
-#pragma unroll
+#pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
                     if (r < K) {
@@ -1522,7 +1556,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 hit = sh.bi[1] != 0;
                 const Fx Cn = ufx(Fx{sh.bu[0], sh.bu[1]});
                 __syncthreads();
-#pragma unroll
+#pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
                     if (r <= rend) {
@@ -1547,7 +1581,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             }
             if (ex) {
                 // X~ <- post-jump state of replica K (1-based), then a new cycle.
-#pragma unroll
+#pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
                     if (r == K - 1) {
@@ -1563,7 +1597,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 Kx = K;
                 break;
             }
-#pragma unroll
+#pragma unroll kUK
             for (int k = 0; k < RPL; ++k) apply_dx<NS>(Y[k], dxk[k]);
         }
         __syncthreads();

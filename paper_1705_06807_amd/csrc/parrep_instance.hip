@@ -41,6 +41,10 @@ hipError_t PARREP_FN(const DevInst* d, int n, int m, int rpl, int mode, uint32_t
             case 1: return dev::launch_instance<NS, 4, 1, WV>(d, n, mode, hc, hmr, tab_lds, st);
             case 4: return dev::launch_instance<NS, 4, 4, WV>(d, n, mode, hc, hmr, tab_lds, st);
             case 16: return dev::launch_instance<NS, 4, 16, WV>(d, n, mode, hc, hmr, tab_lds, st);
+            case 64:
+                if constexpr (WV == 16)
+                    return dev::launch_instance<NS, 4, 64, WV>(d, n, mode, hc, hmr, tab_lds, st);
+                return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }
@@ -48,6 +52,10 @@ hipError_t PARREP_FN(const DevInst* d, int n, int m, int rpl, int mode, uint32_t
         case 1: return dev::launch_instance<NS, 8, 1, WV>(d, n, mode, hc, hmr, tab_lds, st);
         case 4: return dev::launch_instance<NS, 8, 4, WV>(d, n, mode, hc, hmr, tab_lds, st);
         case 16: return dev::launch_instance<NS, 8, 16, WV>(d, n, mode, hc, hmr, tab_lds, st);
+        case 64:
+            if constexpr (WV == 16)
+                return dev::launch_instance<NS, 8, 64, WV>(d, n, mode, hc, hmr, tab_lds, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

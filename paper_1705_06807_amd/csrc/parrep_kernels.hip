@@ -200,7 +200,7 @@ using namespace dev;
 
 bool shape_supported(LaunchShape s) {
     const bool ns_ok = s.ns == 1 || s.ns == 2 || s.ns == 4;
-    const bool rpl_ok = s.rpl == 1 || s.rpl == 4 || s.rpl == 16;
+    const bool rpl_ok = s.rpl == 1 || s.rpl == 4 || s.rpl == 16 || (s.rpl == 64 && s.waves == 16);
     const bool w_ok = s.waves == 1 || s.waves == 4 || s.waves == 16;
     const bool m_ok = s.m >= 1 && s.m <= kMaxM;
     return ns_ok && rpl_ok && w_ok && m_ok;
@@ -212,7 +212,8 @@ LaunchShape choose_shape(int R, int ns, int m) {
     if (R <= 256) return {4, 1, nsv, m};
     if (R <= 1024) return {4, 4, nsv, m};
     if (R <= 4096) return {4, 16, nsv, m};
-    return {16, 16, nsv, m};
+    if (R <= 16384) return {16, 16, nsv, m};
+    return {64, 16, nsv, m};
 }
 
 #define PARREP_DECL(NSv, Wv)                                                                  \
@@ -254,7 +255,9 @@ int table_lds_need(const DevInst& d, LaunchShape s) {
 
 int table_lds_doubles(LaunchShape s, int max_need) {
     const size_t xb = xbuf_lds_bytes(s.rpl, s.waves, s.ns);
-    const size_t budget = 56 * 1024;  // leaves room for the static LDS of the kernel
+    // leaves room for the static LDS of the kernel (24 KB more of it with 64
+    // replicas per lane: the survivor masks and counts of 1024 slots)
+    const size_t budget = (s.rpl == 64 ? 32 : 56) * 1024;
     const size_t fit = xb < budget ? (budget - xb) / 8 : 0;
     return (int)(fit < (size_t)max_need ? fit : (size_t)max_need);
 }

@@ -290,6 +290,13 @@ def c2_toggle(seed: int = 0, instance_id: int = 0, omega: float = 50.0, R: int =
         seed=seed, instance_id=instance_id)
 
 
+def c4_toggle(seed: int = 0, instance_id: int = 0, R: int = 65536, T: float = 1e5,
+              omega: float = 150.0, t_cp: float = TOGGLE_T_CP) -> Problem:
+    """Large single run: the toggle switch at Omega = 150 (rarer transitions)
+    with 65536 replicas and horizon 1e5, histogram [0, 1200]^2."""
+    return c2_toggle(seed=seed, instance_id=instance_id, omega=omega, R=R, T=T, t_cp=t_cp)
+
+
 def paper_schlogl_problem(seed: int = 0, instance_id: int = 0, R: int = 100, n_c: int = 5000,
                           n_p: int = 5000, T: float = 1e5, V: float = 25.0) -> Problem:
     """The paper's Schloegl run: STEPS thresholds, W+ = {x <= 25.96} (Sec. IV A)."""

@@ -29,7 +29,7 @@ def _code(B, fn):
 
 BAD_PROBLEMS = [
     ("R=0", lambda p: p.replace(R=0), EINVAL),
-    ("R too large", lambda p: p.replace(R=16385), EINVAL),
+    ("R too large", lambda p: p.replace(R=65537), EINVAL),
     ("T<=0", lambda p: p.replace(T=0.0, t_burn=0.0), EINVAL),
     ("t_burn>=T", lambda p: p.replace(t_burn=p.T), EINVAL),
     ("negative c", lambda p: p.replace(c=(-1.0,) + tuple(p.c[1:])), EINVAL),

@@ -181,7 +181,7 @@ def test_absorbing_state(B, oracle):
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (4, 1), (16, 1), (1, 4), (4, 4), (16, 4), (1, 16),
-                                   (4, 16)])
+                                   (4, 16), (16, 16), (64, 16)])
 def test_launch_shapes_agree(B, oracle, shape):
     import torch
     probs = [_toggle_small(i, R=60, T=100.0) for i in range(3)]
@@ -278,3 +278,43 @@ def test_genetic_switch_solve_parity(B, oracle, case):
         g = _gpu_run(B, p)
         assert o.counters["n_cycle_log"] <= 4096
         assert_same(o, g, what="gs_%s/%d" % (name, i))
+
+
+LARGE_R_CASES = [
+    # more than 16384 replicas: 64 replica slots per lane (rolled loops)
+    ("om5_R20000", lambda i: _toggle_small(i, R=20000, T=30.0), 2),
+    # the large single run at Omega = 150, R = 65536, cut short with t_c = t_p = 0.5
+    ("c4_R65536_short", lambda i: W.c4_toggle(seed=31, instance_id=i, T=100.0, t_cp=0.5), 1),
+]
+
+
+@pytest.mark.parametrize("case", LARGE_R_CASES, ids=[c[0] for c in LARGE_R_CASES])
+def test_large_replica_count_parity(B, oracle, case):
+    name, make, n = case
+    for i in range(n):
+        p = make(i)
+        _flush("case %s instance %d R=%d" % (name, i, p.R))
+        o = oracle.run(p, cycle_log_cap=4096)
+        g = _gpu_run(B, p)
+        assert o.counters["cycles"] >= 1
+        assert_same(o, g, what="%s/%d" % (name, i))
+
+
+def test_full_size_c4_properties(B):
+    """The large single run (toggle Omega = 150, R = 65536, T = 1e5) at full
+    size: too long for the oracle, so properties that hold at any size."""
+    import torch
+    p = W.c4_toggle(seed=0)
+    _flush("full-size C4, one instance")
+    out = B.parrep_solve(p, cycle_log_cap=256)
+    torch.cuda.synchronize()
+    h = out.to_host()
+    assert h.counters["spill_overflow"] == 0 and h.counters["status"] == 0
+    assert h.T_s == p.T
+    assert h.hist.sum() + h.outside == pytest.approx(p.T, rel=1e-12)
+    assert h.hist_w.sum() + h.outside_w == pytest.approx(p.T - p.t_burn, rel=1e-12)
+    c = h.counters
+    # every S2 and S3 round moves all replicas; S3 credits R per round but the last
+    assert c["ev_dephase"] == c["s2_rounds"] * p.R
+    assert c["ev_par_credited"] + c["ev_par_discarded"] == c["s3_rounds"] * p.R
+    assert np.all(h.fim.diagonal() > 0)
