@@ -51,14 +51,21 @@ TRAFFIC = {"sources_sha256": "6bbb04b2208d7f9e326dbb0c68cc60917cb0b7e6e875793304
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
 
+# The instance kernel is compiled from these files (its translation unit and
+# every header it includes).
+KERNEL_SOURCES = ("paper_1705_06807_amd/csrc/parrep_instance.hip",
+                  "paper_1705_06807_amd/csrc/parrep_device.h",
+                  "paper_1705_06807_amd/csrc/parrep_internal.h",
+                  "paper_1705_06807_amd/csrc/parrep_neglog.h",
+                  "include/parrep.h")
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1705_06807_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

@@ -79,6 +79,10 @@ def lib():
         L.or_fim_rer.argtypes = [C.POINTER(Net), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]
+        dp = C.POINTER(C.c_double)
+        L.or_estimate.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_double, dp, dp, dp,
+                                  dp, dp, dp]
+        L.or_estimate.restype = None
         L.or_run.argtypes = [C.POINTER(Net), C.POINTER(ProblemS), C.POINTER(ResultS)]
         L.or_run.restype = C.c_int
         L.or_dephase.argtypes = [C.POINTER(Net), C.POINTER(ProblemS), C.POINTER(C.c_int32),
@@ -192,6 +196,25 @@ def fim_rer(net, c, x, rer_eps=None):
                      1 if rer_eps is not None else 0, _ptr(xx, C.c_int32),
                      _ptr(fim, C.c_double), _ptr(rer, C.c_double))
     return fim[:np_ * np_].reshape(np_, np_).copy(), rer[:np_].copy()
+
+
+def estimate(fim, rer, y, window):
+    """Multi-run estimators (Sec. III) of n runs: fim (n, p, p), rer (n, p),
+    y (n, s) window integrals.  Returns a dict of fim_mean (p, p), fim_hw (p),
+    rer_mean (p), y_mean (s), iaf (s), bound (s, p)."""
+    fim = np.ascontiguousarray(fim, dtype=np.float64)
+    rer = np.ascontiguousarray(rer, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n, p = rer.shape
+    s = y.shape[1]
+    assert fim.shape == (n, p, p) and y.shape[0] == n and n >= 2
+    out = dict(fim_mean=np.zeros((p, p)), fim_hw=np.zeros(p), rer_mean=np.zeros(p),
+               y_mean=np.zeros(s), iaf=np.zeros(s), bound=np.zeros((s, p)))
+    d = C.c_double
+    lib().or_estimate(n, p, s, _ptr(fim, d), _ptr(rer, d), _ptr(y, d), float(window),
+                      _ptr(out["fim_mean"], d), _ptr(out["fim_hw"], d), _ptr(out["rer_mean"], d),
+                      _ptr(out["y_mean"], d), _ptr(out["iaf"], d), _ptr(out["bound"], d))
+    return out
 
 
 class OracleResult:

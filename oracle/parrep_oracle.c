@@ -649,3 +649,44 @@ int or_parallel(const or_net* net, const or_problem* pb, const int32_t* init, ui
     *credited = fx_to_double(s.C);
     return rc == 1 ? 0 : -1;
 }
+
+/* ------------------------------------------------------------------ */
+/* Multi-run estimators (Sec. III): sample means over the runs, the    */
+/* 95 % half-width of the mean FIM diagonal, the IAF of f = x_i from   */
+/* the spread of the window integrals, and the stationary sensitivity  */
+/* bounds sqrt(IAF_f v^T FIM v) with v = e_k.  Plain two-pass sums in  */
+/* run order.                                                          */
+/* ------------------------------------------------------------------ */
+static void mean_and_sq(int n, const double* v, int stride, int e, double* mean, double* sq)
+{
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += v[(size_t)r * stride + e];
+    double m = s / (double)n;
+    double q = 0.0;
+    for (int r = 0; r < n; ++r) {
+        double d = v[(size_t)r * stride + e] - m;
+        q += d * d;
+    }
+    *mean = m;
+    *sq = q;
+}
+
+void or_estimate(int n, int np, int ns, const double* fim, const double* rer, const double* y,
+                 double window, double* fim_mean, double* fim_hw, double* rer_mean,
+                 double* y_mean, double* iaf, double* bound)
+{
+    double q;
+    for (int e = 0; e < np * np; ++e) {
+        mean_and_sq(n, fim, np * np, e, &fim_mean[e], &q);
+        if (e % (np + 1) == 0)
+            fim_hw[e / (np + 1)] = 1.96 * (sqrt(q / (double)(n - 1)) / sqrt((double)n));
+    }
+    for (int k = 0; k < np; ++k) mean_and_sq(n, rer, np, k, &rer_mean[k], &q);
+    for (int i = 0; i < ns; ++i) {
+        mean_and_sq(n, y, ns, i, &y_mean[i], &q);
+        iaf[i] = q / (window * (double)(n - 1));
+    }
+    for (int i = 0; i < ns; ++i)
+        for (int k = 0; k < np; ++k) bound[i * np + k] = sqrt(iaf[i] * fim_mean[k * np + k]);
+}
+

@@ -116,6 +116,15 @@ int or_dephase(const or_net* net, const or_problem* pb, const int32_t* xt, uint3
                int32_t* Y_out, int64_t* rounds_out);
 int or_parallel(const or_net* net, const or_problem* pb, const int32_t* init, uint32_t cycle,
                 int64_t max_rounds, int64_t* nstar_K, int32_t* exit_state, double* credited);
+/* Multi-run estimators of Sec. III over n >= 2 independent runs of one
+ * problem: fim (n x np*np), rer (n x np) and y (n x ns, window integrals)
+ * per run, window = T - t_burn.  Outputs: means of fim, rer and y; the 95 %
+ * half-width 1.96 sd / sqrt(n) of each FIM diagonal entry; iaf[i] =
+ * sum_r (y_i^r - mean)^2 / (window (n - 1)); bound[i*np + k] =
+ * sqrt(iaf[i] fim_mean[k,k]). */
+void or_estimate(int n, int np, int ns, const double* fim, const double* rer, const double* y,
+                 double window, double* fim_mean, double* fim_hw, double* rer_mean,
+                 double* y_mean, double* iaf, double* bound);
 
 #ifdef __cplusplus
 }

@@ -105,6 +105,8 @@ def lib():
             L.parrep_solve_batch.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Problem),
                                              C.POINTER(Result), C.POINTER(Launch), vp]
             L.parrep_philox.argtypes = [vp, C.c_int64, vp, vp, vp]
+            L.parrep_estimate.argtypes = [vp, C.c_int32, C.POINTER(vp), C.c_int32, C.c_int32,
+                                          C.c_double, vp, vp]
             L.parrep_events.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_int64, vp, vp, vp, vp,
                                         vp, vp]
             L.parrep_dephase_only.argtypes = [vp, vp, C.POINTER(Problem), C.POINTER(C.c_int32),
@@ -318,6 +320,34 @@ def parrep_solve_batch(problems: Sequence[W.Problem], ctx: Optional[Context] = N
         la.event_before, la.event_after = events[0].cuda_event, events[1].cuda_event
     _check(lib().parrep_solve_batch(ctx.h, n, nets, ps, rs, C.byref(la), _stream_ptr(stream)))
     return outs
+
+
+EST_FIM, EST_FIM_HW, EST_RER, EST_Y, EST_IAF, EST_BOUND, EST_LEN = 0, 64, 72, 80, 84, 88, 120
+
+
+def parrep_estimate(outputs: Sequence["Outputs"], ctx: Optional[Context] = None, stream=None):
+    """Multi-run estimators (Sec. III) of the runs in outputs (one problem's
+    independent runs) on the device; returns the PARREP_EST_* buffer (device
+    tensor of EST_LEN doubles)."""
+    torch = _torch()
+    ctx = ctx or context()
+    p = outputs[0].problem
+    out = torch.empty(EST_LEN, dtype=torch.float64, device=ctx.torch_device)
+    ptrs = (C.c_void_p * len(outputs))(*[o.stats.data_ptr() for o in outputs])
+    _check(lib().parrep_estimate(ctx.h, len(outputs), ptrs, p.net.n_params, p.net.n_species,
+                                 p.T - p.t_burn, C.c_void_p(out.data_ptr()),
+                                 _stream_ptr(stream)))
+    return out
+
+
+def split_estimates(est, n_params: int, n_species: int) -> dict:
+    """Host view of an estimates buffer, with the oracle's field names."""
+    e = est.cpu().numpy() if hasattr(est, "cpu") else np.asarray(est)
+    p, s = n_params, n_species
+    return dict(fim_mean=e[EST_FIM:EST_FIM + p * p].reshape(p, p).copy(),
+                fim_hw=e[EST_FIM_HW:EST_FIM_HW + p].copy(), rer_mean=e[EST_RER:EST_RER + p].copy(),
+                y_mean=e[EST_Y:EST_Y + s].copy(), iaf=e[EST_IAF:EST_IAF + s].copy(),
+                bound=e[EST_BOUND:EST_BOUND + s * p].reshape(s, p).copy())
 
 
 def parrep_philox(ctr_key, ctx: Optional[Context] = None, stream=None):

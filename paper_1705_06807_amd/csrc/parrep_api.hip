@@ -1,4 +1,5 @@
-// parrep_api.hip -- the C ABI of libparrep (declared in include/parrep.h):
+// parrep_api.hip -- the C ABI of libparrep (declared in include/parrep.h and
+// include/parrep_estimate.h):
 // argument validation, device descriptors, scratch, and kernel launches.
 #include <algorithm>
 #include <cmath>
@@ -11,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/parrep_estimate.h"
 #include "parrep_host.h"
 #include "parrep_neglog.h"
 
@@ -648,6 +650,34 @@ int parrep_parallel_only(parrep_ctx* ctx, const parrep_net* net, const parrep_pr
     std::lock_guard<std::mutex> lk(ctx->mu);
     return run_batch(ctx, insts, kModeParallelOnly, cycle, max_rounds, (hipStream_t)stream,
                      nullptr, nullptr, nullptr);
+}
+
+int parrep_estimate(parrep_ctx* ctx, int32_t n_runs, const double* const* stats_ptrs,
+                    int32_t n_params, int32_t n_species, double window, double* out,
+                    void* stream) {
+    if (!ctx || !stats_ptrs || !out) return fail(PARREP_EINVAL, "NULL argument");
+    if (n_runs < 2) return fail(PARREP_EINVAL, "n_runs must be >= 2");
+    if (n_params < 1 || n_params > kMaxP || n_species < 1 || n_species > kMaxS)
+        return fail(PARREP_EINVAL, "n_params or n_species out of range");
+    if (!(window > 0.0) || !std::isfinite(window))
+        return fail(PARREP_EINVAL, "window must be positive and finite");
+    for (int32_t r = 0; r < n_runs; ++r)
+        if (!stats_ptrs[r]) return fail(PARREP_EINVAL, "NULL stats pointer");
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    void* d_ptrs = nullptr;
+    const size_t bytes = sizeof(double*) * (size_t)n_runs;
+    hipError_t e = hipMallocAsync(&d_ptrs, bytes, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    // from pageable host memory: staged before the call returns
+    e = hipMemcpyAsync(d_ptrs, stats_ptrs, bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_estimate(static_cast<const double* const*>(d_ptrs), n_runs, n_params,
+                            n_species, window, out, st);
+    hipError_t ef = hipFreeAsync(d_ptrs, st);
+    if (e != hipSuccess) return hip_fail(e, "estimate launch");
+    return ef == hipSuccess ? PARREP_OK : hip_fail(ef, "hipFreeAsync");
 }
 
 }  // extern "C"

@@ -32,6 +32,11 @@ struct parrep_net {
 };
 
 namespace parrep {
+
+// Multi-run estimators: d_stats is a device array of n device pointers.
+hipError_t launch_estimate(const double* const* d_stats, int n, int np, int ns, double window,
+                           double* out, hipStream_t stream);
+
 namespace host {
 
 int fail(int code, const std::string& msg);

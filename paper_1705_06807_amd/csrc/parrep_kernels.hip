@@ -1,6 +1,7 @@
 // parrep_kernels.hip -- non-templated kernels of libparrep (accumulator
 // zeroing, FIM/RER finalize, test hooks) and the instance-kernel dispatch.
 #include "parrep_device.h"
+#include "../../include/parrep_estimate.h"
 
 namespace parrep {
 namespace dev {
@@ -194,9 +195,61 @@ __global__ void __launch_bounds__(256) k_events(const DevInst* __restrict__ inst
     Jo[i] = J;
 }
 
+// ---------------------------------------------------------------------------
+// Multi-run estimators (Sec. III): one thread per statistic, two-pass sums
+// over the runs in run order; then the bounds from the means.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(128) k_estimate(const double* const* __restrict__ st, int n,
+                                                  int np, int ns, double window, double* out) {
+    __shared__ double fdiag[kMaxP], iafs[kMaxS];
+    const int t = threadIdx.x;
+    for (int i = t; i < PARREP_EST_LEN; i += blockDim.x) out[i] = 0.0;
+    __syncthreads();
+    int src = -1;
+    if (t < np * np) src = PARREP_ST_FIM + t;
+    else if (t < np * np + np) src = PARREP_ST_RER + (t - np * np);
+    else if (t < np * np + np + ns) src = PARREP_ST_Y + (t - np * np - np);
+    if (src >= 0) {
+        double s = 0.0;
+        for (int r = 0; r < n; ++r) s += st[r][src];
+        const double m = s / (double)n;
+        double q = 0.0;
+        for (int r = 0; r < n; ++r) {
+            const double d = st[r][src] - m;
+            q += d * d;
+        }
+        if (t < np * np) {
+            out[PARREP_EST_FIM + t] = m;
+            if (t % (np + 1) == 0) {
+                const int k = t / (np + 1);
+                out[PARREP_EST_FIM_HW + k] =
+                    1.96 * (sqrt(q / (double)(n - 1)) / sqrt((double)n));
+                fdiag[k] = m;
+            }
+        } else if (t < np * np + np) {
+            out[PARREP_EST_RER + (t - np * np)] = m;
+        } else {
+            const int i = t - np * np - np;
+            const double iaf = q / (window * (double)(n - 1));
+            out[PARREP_EST_Y + i] = m;
+            out[PARREP_EST_IAF + i] = iaf;
+            iafs[i] = iaf;
+        }
+    }
+    __syncthreads();
+    if (t < ns * np) out[PARREP_EST_BOUND + t] = sqrt(iafs[t / np] * fdiag[t % np]);
+}
+
 }  // namespace dev
 
 using namespace dev;
+
+hipError_t launch_estimate(const double* const* d_stats, int n, int np, int ns, double window,
+                           double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_estimate, dim3(1), dim3(128), 0, stream, d_stats, n, np, ns, window,
+                       out);
+    return hipGetLastError();
+}
 
 bool shape_supported(LaunchShape s) {
     const bool ns_ok = s.ns == 1 || s.ns == 2 || s.ns == 4;

@@ -1,7 +1,8 @@
 """Host-side checks of the C ABI (CPU, no GPU calls): the library loads and
-exports every function include/parrep.h declares; the binding's structs have
-the header's layout; the input generators produce valid problems."""
+exports every function the headers in include/ declare; the binding's structs
+have the header's layout; the input generators produce valid problems."""
 import ctypes
+import glob
 import os
 import re
 
@@ -15,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "parrep.h")
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(parrep_[a-z_0-9]+)\s*\(",
                        src, flags=re.M)
@@ -37,7 +38,7 @@ def test_header_declares_the_boundary():
               "parrep_problem_nbins", "parrep_plan_create", "parrep_plan_update",
               "parrep_plan_launch", "parrep_plan_destroy", "parrep_autotune",
               "parrep_server_create", "parrep_server_submit", "parrep_server_poll",
-              "parrep_server_cancel", "parrep_server_destroy"):
+              "parrep_server_cancel", "parrep_server_destroy", "parrep_estimate"):
         assert n in names
 
 
@@ -73,6 +74,12 @@ def test_header_constants_match_binding():
     for name, v in (("PARREP_ST_FIM", B.ST_FIM), ("PARREP_ST_RER", B.ST_RER),
                     ("PARREP_ST_Y", B.ST_Y)):
         assert int(re.search(r"%s = (\d+)" % name, src).group(1)) == v
+    est = open(os.path.join(ROOT, "include", "parrep_estimate.h")).read()
+    for name, v in (("PARREP_EST_FIM", B.EST_FIM), ("PARREP_EST_FIM_HW", B.EST_FIM_HW),
+                    ("PARREP_EST_RER", B.EST_RER), ("PARREP_EST_Y", B.EST_Y),
+                    ("PARREP_EST_IAF", B.EST_IAF), ("PARREP_EST_BOUND", B.EST_BOUND),
+                    ("PARREP_EST_LEN", B.EST_LEN)):
+        assert int(re.search(r"%s = (\d+)" % name, est).group(1)) == v
 
 
 def test_validation_without_a_device(so):

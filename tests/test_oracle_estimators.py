@@ -205,3 +205,70 @@ def test_paper_tables_from_exact_laws():
     # the bounds dominate the sensitivities
     for k in range(4):
         assert abs(E.schlogl_paper_sensitivity(k, V=V)) <= g["bound_c%d" % (k + 1)][0]
+
+
+# ----------------------------------------------------------------------------
+# Multi-run estimators (Sec. III): the oracle's or_estimate
+# ----------------------------------------------------------------------------
+
+def test_estimate_hand_example(oracle):
+    """Three runs of a 2-parameter, 1-species problem, window 2, by hand:
+    FIM_11 = 1, 2, 3 -> mean 2, sample variance 1, half-width 1.96/sqrt(3);
+    Y = 10, 12, 14 -> mean 12, squared deviations 8, IAF = 8 / (2 * 2) = 2;
+    bound_1 = sqrt(2 * 2) = 2, bound_2 = sqrt(2 * 8) = 4."""
+    fim = np.array([[[1.0, 0.5], [0.5, 8.0]], [[2.0, 0.5], [0.5, 8.0]], [[3.0, 0.5], [0.5, 8.0]]])
+    rer = np.array([[0.1, 0.2], [0.3, 0.2], [0.5, 0.2]])
+    y = np.array([[10.0], [12.0], [14.0]])
+    e = oracle.estimate(fim, rer, y, window=2.0)
+    assert e["fim_mean"].tolist() == [[2.0, 0.5], [0.5, 8.0]]
+    assert e["fim_hw"][0] == pytest.approx(1.96 / math.sqrt(3.0), rel=1e-15)
+    assert e["fim_hw"][1] == 0.0
+    assert e["rer_mean"] == pytest.approx([0.3, 0.2], rel=1e-15)
+    assert e["y_mean"].tolist() == [12.0]
+    assert e["iaf"].tolist() == [2.0]
+    assert e["bound"].tolist() == [[2.0, 4.0]]
+
+
+def test_estimate_reproduces_table3_from_table2(oracle):
+    """Table III's bounds are sqrt(IAF FIM_kk) of Table II's FIM and the printed
+    IAF 5.87e5 (Sec. IV A): two runs whose FIM diagonals average to Table II's
+    values (FIM_22 taken exact, A20) and whose window integrals are spread so
+    that the IAF is 5.87e5; the estimator's bounds match Table III to 0.5 %."""
+    g = _golden()
+    V = 25.0
+    c = np.array(W.SCHLOGL_PAPER_C)
+    x = np.arange(401)
+    pi = E.schlogl_paper_pi(400, V=V)
+    lam = E.schlogl_paper_rates(x, V=V)
+    fim22 = float(np.dot(pi, lam[1]) / c[1] ** 2)
+    diag = np.array([g["fim_11"][0], fim22, g["fim_33"][0], g["fim_44"][0]])
+    fim = np.stack([np.diag(diag * 0.9), np.diag(diag * 1.1)])
+    rer = np.zeros((2, 4))
+    window = 1e5
+    # two runs: sum of squared deviations = 2 d^2 = IAF * window * (n - 1)
+    d = math.sqrt(g["iaf_x"][0] * window / 2.0)
+    y = np.array([[7.2e6 - d], [7.2e6 + d]])
+    e = oracle.estimate(fim, rer, y, window=window)
+    assert e["iaf"][0] == pytest.approx(g["iaf_x"][0], rel=1e-12)
+    assert e["fim_mean"].diagonal() == pytest.approx(diag, rel=1e-15)
+    for k in range(4):
+        assert e["bound"][0, k] == pytest.approx(g["bound_c%d" % (k + 1)][0], rel=0.005), k
+
+
+def test_estimate_is_unbiased(oracle):
+    """Runs with i.i.d. normal FIM entries (variance s2) and window integrals of
+    variance v * window: averaged over 400 batches of 20 runs, the squared
+    half-width times n / 1.96^2 estimates s2 and the IAF estimates v, both to
+    within the sampling error of the average (about 1.6 %)."""
+    rng = np.random.default_rng(3)
+    n, reps, window, s2, v = 20, 400, 50.0, 4.0, 3.0
+    hw2, iafs = [], []
+    for _ in range(reps):
+        fim = np.zeros((n, 1, 1))
+        fim[:, 0, 0] = 10.0 + math.sqrt(s2) * rng.standard_normal(n)
+        y = (100.0 + math.sqrt(v * window) * rng.standard_normal(n))[:, None]
+        e = oracle.estimate(fim, np.zeros((n, 1)), y, window=window)
+        hw2.append(e["fim_hw"][0] ** 2 * n / 1.96 ** 2)
+        iafs.append(e["iaf"][0])
+    assert np.mean(hw2) == pytest.approx(s2, rel=0.05)
+    assert np.mean(iafs) == pytest.approx(v, rel=0.05)
