@@ -36,7 +36,7 @@ METRIC = "SSA events/s on 1 GPU (% VALU peak); batched/served ParRep solves/s + 
 VALU_SLOTS_PER_EVENT = 105
 # FP64 VALU instructions per event in the built kernel (rocprofv3 counters
 # SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 over events, toggle workload).
-FP64_OPS_PER_EVENT_ISA = 28.5
+FP64_OPS_PER_EVENT_ISA = 28.44
 # MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz, a wave64 VALU op takes 4 cycles
 # -> 256*4*16*2.4e9 = 3.93e13 lane-op slots per second.
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
@@ -46,8 +46,8 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by what the
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
-TRAFFIC = {"sources_sha256": "6bbb04b2208d7f9e326dbb0c68cc60917cb0b7e6e8757933047789fb540fc9e7",
-           "fetch_kib": 71862.25, "write_kib": 894804364.40625,
+TRAFFIC = {"sources_sha256": "8effd3da3f30e10bf4e08b71f010a15430cceabffda88b2f1825b6c57f714cfa",
+           "fetch_kib": 722864.0, "write_kib": 2843298128.96875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
 
