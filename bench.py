@@ -42,12 +42,14 @@ FP64_OPS_PER_EVENT_ISA = 28.44
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 
-# HBM traffic of one launch of the instance kernel at the benchmark workload,
+# HBM traffic of one launch of the instance kernel at the benchmark workload
+# (the batch of `instances` trajectories),
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by what the
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
-TRAFFIC = {"sources_sha256": "8effd3da3f30e10bf4e08b71f010a15430cceabffda88b2f1825b6c57f714cfa",
-           "fetch_kib": 722864.0, "write_kib": 2843298128.96875,
+TRAFFIC = {"instances": 32768,
+           "sources_sha256": "8effd3da3f30e10bf4e08b71f010a15430cceabffda88b2f1825b6c57f714cfa",
+           "fetch_kib": 1447148.8125, "write_kib": 5686557758.21875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
 
@@ -69,9 +71,11 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def traffic_bytes():
+def traffic_bytes(instances: int):
     t = TRAFFIC
     if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    if instances != t["instances"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
@@ -217,7 +221,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=16384,
+    ap.add_argument("--instances", type=int, default=32768,
                     help="independent trajectories per step")
     ap.add_argument("--T", type=float, default=2e4)
     ap.add_argument("--rpl", type=int, default=0, help="replicas per lane (0 = library choice)")
@@ -338,7 +342,7 @@ def main():
             "peak": VALU_PEAK_SLOTS / 1e12,
             "unit": "T VALU lane-slots/s",
             "frac": achieved / VALU_PEAK_SLOTS,
-            "traffic": traffic_bytes(),
+            "traffic": traffic_bytes(args.instances),
             "kernel_ms": k_avg,
             "ops_per_event": VALU_SLOTS_PER_EVENT,
             "fp64_ops_per_event_isa": FP64_OPS_PER_EVENT_ISA,
