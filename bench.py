@@ -48,7 +48,7 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "8effd3da3f30e10bf4e08b71f010a15430cceabffda88b2f1825b6c57f714cfa",
+           "sources_sha256": "7f5d723f83d609024947b0be1677a63e3af5e9511648998b515b57b46d656a17",
            "fetch_kib": 1447148.8125, "write_kib": 5686557758.21875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
@@ -246,7 +246,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs each ParRep instance on a single "
+        print("bench.py measures one GPU only: the library runs each ParRep instance on a single "
               "device and has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

@@ -49,7 +49,7 @@ typedef enum {
     PARREP_EINVAL = -1,       /* an argument is out of range or inconsistent   */
     PARREP_ENOMEM = -2,       /* device or host allocation failed               */
     PARREP_EDEVICE = -3,      /* a HIP call failed                              */
-    PARREP_EUNSUPPORTED = -4, /* valid input this build does not handle         */
+    PARREP_EUNSUPPORTED = -4, /* valid input the library does not handle       */
     PARREP_EBUSY = -5,        /* result not ready yet (server poll)             */
     PARREP_ECANCELLED = -6    /* request was cancelled                          */
 } parrep_status;
