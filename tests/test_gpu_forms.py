@@ -160,3 +160,52 @@ def test_server_rse_target_and_cancel(B):
     with pytest.raises(B.ParrepError, match="cancelled"):
         srv.poll(t2)
     srv.close()
+
+
+def _general_mix():
+    # general kernels (4 species, 6 reactions: the genetic switch at V = 240)
+    # beside narrow ones, and one instance with 64 replica slots per lane
+    gs = [W.genetic_switch_problem(seed=12, instance_id=i, V=240.0, R=R, n_c=300, n_p=300,
+                                   T=300.0).replace(hist_hi=(1, 1, 8, 700))
+          for i, R in enumerate((8, 100, 900))]
+    big = [W.c2_toggle(seed=13, instance_id=0, omega=5.0, R=20000, T=6.0, t_cp=1.0)
+           .replace(hist_hi=(40, 40))]
+    return gs + big + _mixed(seed=2, n=2)
+
+
+def test_plan_with_general_kernels_and_large_r(B, oracle):
+    import torch
+    probs = _general_mix()
+    _flush("plan over %d instances, R in %s" % (len(probs), sorted(p.R for p in probs)))
+    eager = _host(B.parrep_solve_batch(probs, cycle_log_cap=0))
+    plan = B.Plan(probs)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        B.parrep_solve(W.c1_schlogl(seed=9, instance_id=rep, T=5.0), cycle_log_cap=0)
+        torch.cuda.synchronize()
+        got = [o.to_host() for o in plan.outputs]
+        for i, (g, e) in enumerate(zip(got, eager)):
+            assert_gpu_same(g, e, what="replay %d instance %d" % (rep, i))
+    for i in (0, 3):  # a genetic switch instance and the large-R one against the oracle
+        o = oracle.run(probs[i], cycle_log_cap=0)
+        got[i].cycle_log = None
+        o.cycle_log = None
+        assert_same(o, got[i], what="plan vs oracle %d" % i)
+    plan.close()
+
+
+def test_server_with_general_kernels(B):
+    reqs = [(p, 2) for p in _general_mix()[:4]]
+    srv = B.Server(n_streams=4)
+    tickets = [srv.submit(p, min_runs=n, max_runs=n) for p, n in reqs]
+    _flush("submitted %d requests" % len(tickets))
+    results = [srv.poll(t) for t in tickets]
+    srv.close()
+    for (p, n), (pooled, info) in zip(reqs, results):
+        alone = _pooled_alone(B, p, n)
+        assert info["runs"] == n and info["status"] == 0
+        assert info["events"] == sum(a.events for a in alone)
+        assert pooled.T_s == pytest.approx(sum(a.T_s for a in alone), rel=1e-15)
+        assert _same_float(pooled.hist, sum(a.hist for a in alone))
+        assert _same_float(pooled.fim, sum(a.fim for a in alone) / n)
