@@ -131,3 +131,11 @@ def test_workload_generators_are_valid():
     arrivals, reqs = W.c5_requests(seed=1, n=40)
     assert len(reqs) == 40 and all(256 <= p.R <= 16384 for p in reqs)
     assert all(b >= a for a, b in zip(arrivals[:-1], arrivals[1:]))
+
+
+def test_counter_names_line_up_with_the_oracle(oracle):
+    # the two sides name the same counters in the same order, except the last
+    # slot: the library's spill-overflow count, the oracle's reserved word
+    from oracle import oracle as O
+    assert B.COUNTER_NAMES[:-1] == O.COUNTER_NAMES[:-1]
+    assert B.COUNTER_NAMES[-1] == "spill_overflow" and O.COUNTER_NAMES[-1] == "reserved"
