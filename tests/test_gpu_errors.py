@@ -94,3 +94,7 @@ def test_net_of_another_context_rejected(B):
     rc = binding.lib().parrep_solve(ctx.h, net_other, C.byref(ps), C.byref(rs), None)
     assert rc == EINVAL
     assert "another context" in binding.lib().parrep_last_error().decode()
+
+
+def test_empty_batch_rejected(B):
+    assert _code(B, lambda: B.parrep_solve_batch([])) == EINVAL

@@ -123,6 +123,9 @@ C1_CASES = [
     ("c1_budget", lambda i: W.c1_schlogl(seed=5, instance_id=i).replace(max_events=20000 + 997 * i)),
     ("c1_narrow_hist", lambda i: W.c1_schlogl(seed=6, instance_id=i).replace(
         hist_lo=(60,), hist_hi=(110,))),
+    # degenerate thresholds: no decorrelation and no dephasing (every cycle is S3 from X~)
+    ("c1_zero_thresholds", lambda i: W.c1_schlogl(seed=7, instance_id=i).replace(
+        decorr_mode=W.STEPS, decorr=0, dephase_mode=W.STEPS, dephase=0)),
 ]
 
 
@@ -154,6 +157,7 @@ TOGGLE_CASES = [
     ("om5_steps", lambda i: _toggle_small(i, decorr_mode=W.STEPS, decorr=50,
                                           dephase_mode=W.STEPS, dephase=40)),
     ("om5_outside_box", lambda i: _toggle_small(i, hist_lo=(2, 0), hist_hi=(12, 9))),
+    ("om5_time_zero", lambda i: _toggle_small(i, decorr=0.0, dephase=0.0)),
     ("om50_R1024", lambda i: W.c2_toggle(seed=12, instance_id=i, T=20.0, t_cp=1.0)),
     ("om50_R1024_t20", lambda i: W.c2_toggle(seed=13, instance_id=i, T=120.0)),
 ]
