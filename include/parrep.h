@@ -208,10 +208,15 @@ int64_t parrep_problem_nbins(const parrep_net* net, const parrep_problem* prob);
 int parrep_solve(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
                  const parrep_result* res, void* stream);
 
-/* Many independent solves in one launch: count instances, nets[i] and
+/* Many independent solves in one launch: count >= 1 instances, nets[i] and
  * probs[i] (host arrays), res[i] (host array of device-buffer descriptors).
  * Each instance's outputs equal its parrep_solve outputs for any launch
- * shape (integers exactly; floats up to summation order).  launch may be NULL. */
+ * shape (integers exactly; floats up to summation order).  launch may be
+ * NULL; without a forced shape each instance gets: in a batch of no more
+ * instances than the device has CUs and 64 < R <= 256, one replica per lane
+ * over 4 waves; else the autotuned shape of its replica-count bucket; else
+ * the default for R (replicas per lane x waves: R <= 64 1x1, <= 256 4x1,
+ * <= 1024 4x4, <= 4096 4x16, <= 16384 16x16, else 64x16). */
 int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* nets,
                        const parrep_problem* probs, const parrep_result* res,
                        const parrep_launch* launch, void* stream);
