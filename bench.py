@@ -48,7 +48,7 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "a4b1095eb155041f5d64f0116d99a898b61d34c674b7325c4f94e3cea7903724",
+           "sources_sha256": "8f9bd35a6fb8388a8e07797c06c268b69044f39c07f8231bd759a577c567f7bb",
            "fetch_kib": 1447148.8125, "write_kib": 5686557758.21875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 

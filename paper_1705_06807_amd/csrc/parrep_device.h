@@ -813,96 +813,6 @@ __device__ __forceinline__ bool credit_event(const DevInst* __restrict__ I, cons
 }
 
 
-// FIM / RER integrands at x, times weight w, added through `add(slot, value)`
-// (Sec. III and Appendix A: FIM(x) = sum_j lam_j g_j g_j^T with
-// g_j = grad_c log lam_j; RER_k(x) = sum_j lam_j log(lam_j/lam'_j) - lam_j + lam'_j).
-// Per-thread sums of the window accumulators (compile-time indexed, so they
-// stay in registers): FIM, RER and window integrals.
-struct WinAcc {
-    double fim[kMaxP * kMaxP];
-    double rer[kMaxP];
-    double y[kMaxS];
-};
-
-template <int NS>
-__device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, WinAcc& A) {
-    const int np = S.np;
-    for (int j = 0; j < S.m; ++j) {
-        const double lam = prop_with<NS>(S, j, x, S.c);
-        if (!(lam > 0.0)) continue;
-        double g[kMaxP];
-#pragma unroll
-        for (int p = 0; p < kMaxP; ++p) g[p] = 0.0;
-        const int rp = S.rate_param[j];
-#pragma unroll
-        for (int p = 0; p < kMaxP; ++p)
-            if (p == rp) g[p] += 1.0 / S.c[rp];
-        for (int f = 0; f < S.nf[j]; ++f) {
-            const int kind = S.fkind[j][f];
-            const int hp = S.fhp[j][f];
-            if (kind == PARREP_PARAM) {
-                const double d = 1.0 / S.c[hp];
-#pragma unroll
-                for (int p = 0; p < kMaxP; ++p)
-                    if (p == hp) g[p] += d;
-            } else if (kind == PARREP_HILL_SWITCH) {
-                // phi = lo + (hi - lo) s: d/dlo = 1 - s, d/dhi = s,
-                // d/dK = -(hi - lo) n s (1 - s) / K, each over phi
-                const int xs = pick<NS>(x, S.fsp[j][f]);
-                const int p2 = S.fp2[j][f], p3 = S.fp3[j][f], n = S.ford[j][f];
-                const double lo = S.c[hp], hi = S.c[p2], K = S.c[p3];
-                const double phi = switch_val(xs, n, lo, hi, K);
-                if (!(phi > 0.0)) continue;
-                const double y = (double)xs / K;
-                double q = y;
-                for (int i = 1; i < n; ++i) q = q * y;
-                const double s = q / (1.0 + q);
-                const double dlo = (1.0 - s) / phi, dhi = s / phi;
-                const double dK = -(hi - lo) * n * s * (1.0 - s) / (K * phi);
-#pragma unroll
-                for (int p = 0; p < kMaxP; ++p) {
-                    if (p == hp) g[p] += dlo;
-                    if (p == p2) g[p] += dhi;
-                    if (p == p3) g[p] += dK;
-                }
-            } else if (kind == PARREP_HILL_REP) {
-                const double y = (double)pick<NS>(x, S.fsp[j][f]) / S.fK[j][f];
-                if (!(y > 0.0)) continue;
-                const double q = hill_pow(y, S.fhint[j][f], S.c[hp]);
-                const double d = -q * log(y) / (1.0 + q);
-#pragma unroll
-                for (int p = 0; p < kMaxP; ++p)
-                    if (p == hp) g[p] += d;
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < kMaxP; ++a)
-#pragma unroll
-            for (int bb = 0; bb < kMaxP; ++bb)
-                if (a < np && bb < np) A.fim[a * kMaxP + bb] += w * (lam * g[a] * g[bb]);
-    }
-    if (S.use_rer) {
-#pragma unroll
-        for (int kp = 0; kp < kMaxP; ++kp) {
-            if (kp >= np) continue;
-            double cv[kMaxP];
-#pragma unroll
-            for (int p = 0; p < kMaxP; ++p) cv[p] = (p == kp) ? S.ceps[p] : S.c[p];
-            double h = 0.0;
-            for (int j = 0; j < S.m; ++j) {
-                const double lam = prop_with<NS>(S, j, x, S.c);
-                const double lp = prop_with<NS>(S, j, x, cv);
-                if (lam > 0.0) h += lam * log(lam / lp) - lam + lp;
-                else h += lp;
-            }
-            A.rer[kp] += w * h;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NS; ++i)
-        if (i < S.n) A.y[i] += w * (double)x[i];
-}
-
 // ---------------------------------------------------------------------------
 // Workgroup communication
 // ---------------------------------------------------------------------------

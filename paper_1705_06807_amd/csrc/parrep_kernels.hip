@@ -65,41 +65,143 @@ __global__ void k_zero(const DevInst* __restrict__ insts) {
 // (the integrands depend on the state only, so int F(X_s) ds over the
 // window is sum_x hist_w(x) F(x)), plus the out-of-box accumulators.
 // ---------------------------------------------------------------------------
+// Finalize: hist += hist_w, then the window FIM, RER and integrals of every
+// instance from its window histogram (and the spill slots), divided by the
+// window length.  FIM(x) = sum_j lam_j g_j g_j^T with g_j = grad_c log lam_j
+// and RER_k(x) = sum_j lam_j log(lam_j/lam'_j) - lam_j + lam'_j (Sec. III,
+// Appendix A); the time integrals are sums over visited states, weighted by
+// the window time spent there.  Specialised for up to NS species and NP
+// parameters (so the per-thread accumulators stay in registers); each of the
+// two launches skips the instances of the other.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
 }
 
-// Per instance: completes the full histogram (hist held the time before
-// t_burn, see add_credit), and integrates the FIM, RER and window integrals
-// over the window histogram and the spill table.  Each thread sums its bins
-// in registers; waves reduce by shuffles and add into LDS once.
-template <int NS>
+template <int NP>
+struct WinAcc {
+    double fim[NP * NP];
+    double rer[NP];
+    double y[kMaxS];
+};
+
+template <int NS, int NP>
+__device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, WinAcc<NP>& A) {
+    const int np = S.np;
+    double lamv[kMaxM];
+    for (int j = 0; j < S.m; ++j) lamv[j] = prop_with<NS>(S, j, x, S.c);
+    for (int j = 0; j < S.m; ++j) {
+        const double lam = lamv[j];
+        if (!(lam > 0.0)) continue;
+        double g[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) g[p] = 0.0;
+        const int rp = S.rate_param[j];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            if (p == rp) g[p] += 1.0 / S.c[rp];
+        for (int f = 0; f < S.nf[j]; ++f) {
+            const int kind = S.fkind[j][f];
+            const int hp = S.fhp[j][f];
+            if (kind == PARREP_PARAM) {
+                const double d = 1.0 / S.c[hp];
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    if (p == hp) g[p] += d;
+            } else if (kind == PARREP_HILL_SWITCH) {
+                // phi = lo + (hi - lo) s: d/dlo = 1 - s, d/dhi = s,
+                // d/dK = -(hi - lo) n s (1 - s) / K, each over phi
+                const int xs = pick<NS>(x, S.fsp[j][f]);
+                const int p2 = S.fp2[j][f], p3 = S.fp3[j][f], n = S.ford[j][f];
+                const double lo = S.c[hp], hi = S.c[p2], K = S.c[p3];
+                const double phi = switch_val(xs, n, lo, hi, K);
+                if (!(phi > 0.0)) continue;
+                const double y = (double)xs / K;
+                double q = y;
+                for (int i = 1; i < n; ++i) q = q * y;
+                const double sq = q / (1.0 + q);
+                const double dlo = (1.0 - sq) / phi, dhi = sq / phi;
+                const double dK = -(hi - lo) * n * sq * (1.0 - sq) / (K * phi);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (p == hp) g[p] += dlo;
+                    if (p == p2) g[p] += dhi;
+                    if (p == p3) g[p] += dK;
+                }
+            } else if (kind == PARREP_HILL_REP) {
+                const double y = (double)pick<NS>(x, S.fsp[j][f]) / S.fK[j][f];
+                if (!(y > 0.0)) continue;
+                const double q = hill_pow(y, S.fhint[j][f], S.c[hp]);
+                const double d = -q * log(y) / (1.0 + q);
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    if (p == hp) g[p] += d;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NP; ++a)
+#pragma unroll
+            for (int bb = 0; bb < NP; ++bb)
+                if (a < np && bb < np) A.fim[a * NP + bb] += w * (lam * g[a] * g[bb]);
+    }
+    if (S.use_rer) {
+#pragma unroll
+        for (int kp = 0; kp < NP; ++kp) {
+            if (kp >= np) continue;
+            double cv[kMaxP];
+#pragma unroll
+            for (int p = 0; p < kMaxP; ++p) cv[p] = (p == kp) ? S.ceps[p] : S.c[p];
+            double h = 0.0;
+            for (int j = 0; j < S.m; ++j) {
+                const double lam = lamv[j];
+                const double lp = prop_with<NS>(S, j, x, cv);
+                if (lam > 0.0) h += lam * log(lam / lp) - lam + lp;
+                else h += lp;
+            }
+            A.rer[kp] += w * h;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+        if (i < S.n) A.y[i] += w * (double)x[i];
+}
+
+template <int NS, int NP>
 __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ insts) {
     __shared__ SNet S;
     __shared__ double acc[kAccLen];
     const DevInst* I = insts + blockIdx.x;
+    const bool small = I->net.n_species <= 2 && I->net.n_params <= 4;
+    if (small != (NS <= 2)) return;  // the other launch's instance
     const int tid = threadIdx.x;
     if (tid == 0) load_net(S, I);
     for (int i = tid; i < kAccLen; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
-    WinAcc A;
+    WinAcc<NP> A;
 #pragma unroll
-    for (int i = 0; i < kMaxP * kMaxP; ++i) A.fim[i] = 0.0;
+    for (int i = 0; i < NP * NP; ++i) A.fim[i] = 0.0;
 #pragma unroll
-    for (int i = 0; i < kMaxP; ++i) A.rer[i] = 0.0;
+    for (int i = 0; i < NP; ++i) A.rer[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < kMaxS; ++i) A.y[i] = 0.0;
-    for (int64_t idx = tid; idx < I->nbins; idx += blockDim.x) {
+    // boxes hold fewer than 2^31 bins: 32-bit index arithmetic is exact
+    uint32_t stride[NS], nb[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        stride[i] = (uint32_t)S.hist_stride[i];
+        nb[i] = (uint32_t)S.hist_nb[i];
+    }
+    const uint32_t nbins = (uint32_t)I->nbins;
+    for (uint32_t idx = tid; idx < nbins; idx += blockDim.x) {
         const double h = I->hist_w[idx];
         if (h == 0.0) continue;
         I->hist[idx] += h;
         int x[NS];
 #pragma unroll
-        for (int i = 0; i < NS; ++i)
-            x[i] = S.hist_lo[i] + (int)((idx / S.hist_stride[i]) % S.hist_nb[i]);
-        fim_rer_point<NS>(S, x, h, A);
+        for (int i = 0; i < NS; ++i) x[i] = S.hist_lo[i] + (int)((idx / stride[i]) % nb[i]);
+        fim_rer_point<NS, NP>(S, x, h, A);
     }
     // states outside the box: their window time sits in the spill table
     for (int i = tid; i < kSpillCap; i += blockDim.x) {
@@ -108,20 +210,20 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
         int x[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) x[s] = (int)((sl.key >> (15 * s)) & 0x7FFF);
-        fim_rer_point<NS>(S, x, sl.w, A);
+        fim_rer_point<NS, NP>(S, x, sl.w, A);
     }
     const int np = S.np;
     const bool lead = (tid & 63) == 0;
 #pragma unroll
-    for (int a = 0; a < kMaxP; ++a)
+    for (int a = 0; a < NP; ++a)
 #pragma unroll
-        for (int b = 0; b < kMaxP; ++b) {
+        for (int b = 0; b < NP; ++b) {
             if (a >= np || b >= np) continue;
-            const double v = wave_sum_f64(A.fim[a * kMaxP + b]);
+            const double v = wave_sum_f64(A.fim[a * NP + b]);
             if (lead) atomicAdd(&acc[kAccFim + a * np + b], v);
         }
 #pragma unroll
-    for (int a = 0; a < kMaxP; ++a) {
+    for (int a = 0; a < NP; ++a) {
         if (a >= np) continue;
         const double v = wave_sum_f64(A.rer[a]);
         if (lead) atomicAdd(&acc[kAccRer + a], v);
@@ -321,8 +423,12 @@ hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream) {
 }
 
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream) {
-    // NS of the finalize kernel only sizes the state vector; 4 covers all.
-    hipLaunchKernelGGL((k_finalize<kMaxS>), dim3(n_inst), dim3(256), 0, stream, d_inst);
+    // one launch for instances of at most 2 species and 4 parameters, one
+    // for the rest; each block of the other class returns at once
+    hipLaunchKernelGGL((k_finalize<2, 4>), dim3(n_inst), dim3(256), 0, stream, d_inst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_finalize<kMaxS, kMaxP>), dim3(n_inst), dim3(256), 0, stream, d_inst);
     return hipGetLastError();
 }
 
