@@ -228,11 +228,13 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
  * bucket, else the library default), each group ordered longest first, and
  * setup / zero / the group launches (side by side) / finalize captured into
  * one hipGraph.  Outputs go to the res[i] buffers given at creation.
+ * launch may be NULL; its shape fields force one launch shape as in
+ * parrep_solve_batch (its events are not used: see parrep_plan_run).
  * Problems as in parrep_solve_batch; EINVAL on invalid input, EDEVICE if a
  * HIP call fails (nothing is left allocated then). */
 int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* nets,
                        const parrep_problem* probs, const parrep_result* res,
-                       parrep_plan** out);
+                       const parrep_launch* launch, parrep_plan** out);
 
 /* Replace instance `index`'s problem (host, read during the call) for the
  * following launches: the copy is enqueued on stream, so updates and
@@ -245,6 +247,13 @@ int parrep_plan_update(parrep_plan* plan, int32_t index, const parrep_problem* p
 
 /* Replay the plan's graph on stream (outputs are rewritten each time). */
 int parrep_plan_launch(parrep_plan* plan, void* stream);
+
+/* The same work as a replay, enqueued on stream as individual kernel
+ * launches (the plan's resident descriptors and scratch, no graph), with two
+ * optional hipEvent_t (NULL = none) recorded on stream right before and right
+ * after the instance kernels: the form in which those kernels can be timed
+ * with events. */
+int parrep_plan_run(parrep_plan* plan, void* event_before, void* event_after, void* stream);
 
 /* Waits for the plan's last launch or update, then frees it. */
 void parrep_plan_destroy(parrep_plan* plan);

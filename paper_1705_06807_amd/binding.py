@@ -114,8 +114,10 @@ def lib():
             L.parrep_parallel_only.argtypes = [vp, vp, C.POINTER(Problem), vp, C.c_uint32,
                                                C.c_int64, vp, vp, vp, vp]
             L.parrep_plan_create.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Problem),
-                                             C.POINTER(Result), C.POINTER(vp)]
+                                             C.POINTER(Result), C.POINTER(Launch),
+                                             C.POINTER(vp)]
             L.parrep_plan_update.argtypes = [vp, C.c_int32, C.POINTER(Problem), vp]
+            L.parrep_plan_run.argtypes = [vp, vp, vp, vp]
             L.parrep_plan_launch.argtypes = [vp, vp]
             L.parrep_plan_destroy.argtypes = [vp]
             L.parrep_autotune.argtypes = [vp, vp, C.POINTER(Problem), C.c_int32, C.c_int64,
@@ -421,7 +423,8 @@ class Plan:
     """A batch prepared once and replayed as one hipGraph launch."""
 
     def __init__(self, problems: Sequence[W.Problem], ctx: Optional[Context] = None,
-                 cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None):
+                 cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None,
+                 replicas_per_lane: int = 0, waves: int = 0):
         self.ctx = ctx or context()
         n = len(problems)
         self.problems = list(problems)
@@ -430,12 +433,20 @@ class Plan:
         nets = (C.c_void_p * n)(*[self.ctx.net(p.net).value for p in problems])
         ps = (Problem * n)(*[problem_struct(p) for p in problems])
         rs = (Result * n)(*[o.struct() for o in self.outputs])
+        la = Launch(replicas_per_lane, waves, None, None)
         h = C.c_void_p()
-        _check(lib().parrep_plan_create(self.ctx.h, n, nets, ps, rs, C.byref(h)))
+        _check(lib().parrep_plan_create(self.ctx.h, n, nets, ps, rs, C.byref(la), C.byref(h)))
         self.h = h
 
     def launch(self, stream=None):
         _check(lib().parrep_plan_launch(self.h, _stream_ptr(stream)))
+
+    def run(self, stream=None, events=None):
+        """The plan's work as individual launches (no graph); events: an
+        optional (before, after) torch.cuda.Event pair recorded around the
+        instance kernels."""
+        eb, ea = (events[0].cuda_event, events[1].cuda_event) if events else (None, None)
+        _check(lib().parrep_plan_run(self.h, eb, ea, _stream_ptr(stream)))
 
     def update(self, index: int, p: W.Problem, stream=None):
         ps = problem_struct(p)

@@ -43,7 +43,7 @@ extern "C" {
 
 int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* nets,
                        const parrep_problem* probs, const parrep_result* res,
-                       parrep_plan** out) {
+                       const parrep_launch* launch, parrep_plan** out) {
     if (!ctx || !nets || !probs || !res || !out) return fail(PARREP_EINVAL, "NULL argument");
     if (count < 1) return fail(PARREP_EINVAL, "count < 1");
     parrep_plan* p = new (std::nothrow) parrep_plan();
@@ -52,6 +52,7 @@ int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
     std::vector<DevInst> insts((size_t)count);
     p->nets.assign(nets, nets + count);
     p->nbins.resize(count);
+    int maxR = 1, maxS = 1;
     for (int i = 0; i < count; ++i) {
         if (!nets[i] || nets[i]->ctx != ctx) {
             delete p;
@@ -65,6 +66,24 @@ int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
         }
         fill_inst(insts[i], nets[i], &probs[i], p->nbins[i]);
         attach_result(insts[i], &res[i]);
+        maxR = std::max(maxR, probs[i].R);
+        maxS = std::max(maxS, (int)nets[i]->net.n_species);
+    }
+    LaunchShape forced{};
+    const bool force = launch && (launch->replicas_per_lane > 0 || launch->waves > 0);
+    if (force) {
+        forced = choose_shape(maxR, maxS, kMaxM);
+        forced.rpl = launch->replicas_per_lane > 0 ? launch->replicas_per_lane : forced.rpl;
+        forced.waves = launch->waves > 0 ? launch->waves : forced.waves;
+        int rc = PARREP_OK;
+        if ((int64_t)forced.rpl * forced.waves * 64 < maxR)
+            rc = fail(PARREP_EINVAL, "launch shape holds fewer replicas than R");
+        else if (!shape_supported(forced))
+            rc = fail(PARREP_EUNSUPPORTED, "launch shape not compiled in");
+        if (rc) {
+            delete p;
+            return rc;
+        }
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
     int rc = set_device(ctx);
@@ -73,7 +92,7 @@ int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
         return rc;
     }
     std::vector<int> order;
-    p->groups = group_batch(ctx, insts, &order, nullptr);
+    p->groups = group_batch(ctx, insts, &order, force ? &forced : nullptr);
     p->slot.resize(count);
     for (int k = 0; k < count; ++k) p->slot[order[k]] = k;
     hipError_t e = hipMalloc(&p->base, arena_bytes(insts, false));
@@ -167,6 +186,19 @@ int parrep_plan_launch(parrep_plan* p, void* stream) {
     if (rc) return rc;
     hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    p->last = (hipStream_t)stream;
+    return PARREP_OK;
+}
+
+int parrep_plan_run(parrep_plan* p, void* event_before, void* event_after, void* stream) {
+    if (!p) return fail(PARREP_EINVAL, "NULL plan");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    int rc = set_device(p->ctx);
+    if (rc) return rc;
+    rc = enqueue_batch(p->ctx, static_cast<DevInst*>(p->base), (int)p->insts.size(), p->groups,
+                       kModeSolve, 0, -1, (hipStream_t)stream, (hipEvent_t)event_before,
+                       (hipEvent_t)event_after);
+    if (rc) return rc;
     p->last = (hipStream_t)stream;
     return PARREP_OK;
 }

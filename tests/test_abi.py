@@ -36,7 +36,7 @@ def test_header_declares_the_boundary():
               "parrep_net_destroy", "parrep_solve", "parrep_solve_batch", "parrep_philox",
               "parrep_events", "parrep_dephase_only", "parrep_parallel_only",
               "parrep_problem_nbins", "parrep_plan_create", "parrep_plan_update",
-              "parrep_plan_launch", "parrep_plan_destroy", "parrep_autotune",
+              "parrep_plan_launch", "parrep_plan_run", "parrep_plan_destroy", "parrep_autotune",
               "parrep_server_create", "parrep_server_submit", "parrep_server_poll",
               "parrep_server_cancel", "parrep_server_destroy", "parrep_estimate"):
         assert n in names

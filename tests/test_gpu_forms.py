@@ -209,3 +209,27 @@ def test_server_with_general_kernels(B):
         assert pooled.T_s == pytest.approx(sum(a.T_s for a in alone), rel=1e-15)
         assert _same_float(pooled.hist, sum(a.hist for a in alone))
         assert _same_float(pooled.fim, sum(a.fim for a in alone) / n)
+
+
+def test_plan_run_matches_eager_and_times_the_instance_kernels(B):
+    import torch
+    probs = _mixed(seed=4)
+    eager = _host(B.parrep_solve_batch(probs, cycle_log_cap=0))
+    plan = B.Plan(probs)
+    ev_b = torch.cuda.Event(enable_timing=True)
+    ev_a = torch.cuda.Event(enable_timing=True)
+    # torch creates the HIP events on first record; the library records them again
+    ev_b.record()
+    ev_a.record()
+    for rep in range(2):
+        plan.run(events=(ev_b, ev_a))
+        torch.cuda.synchronize()
+        assert ev_b.elapsed_time(ev_a) > 0.0
+        got = [o.to_host() for o in plan.outputs]
+        for i, (g, e) in enumerate(zip(got, eager)):
+            assert_gpu_same(g, e, what="run %d instance %d" % (rep, i))
+    plan.launch()  # graph replays and runs mix on one plan
+    torch.cuda.synchronize()
+    for i, (g, e) in enumerate(zip([o.to_host() for o in plan.outputs], eager)):
+        assert_gpu_same(g, e, what="replay after runs, instance %d" % i)
+    plan.close()
