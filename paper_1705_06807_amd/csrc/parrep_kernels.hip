@@ -88,7 +88,8 @@ struct WinAcc {
 };
 
 template <int NS, int NP>
-__device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, WinAcc<NP>& A) {
+__device__ void fim_rer_point(const SNet& S, const uint32_t* dep, const int (&x)[NS], double w,
+                              WinAcc<NP>& A) {
     const int np = S.np;
     double lamv[kMaxM];
     for (int j = 0; j < S.m; ++j) lamv[j] = prop_with<NS>(S, j, x, S.c);
@@ -147,6 +148,9 @@ __device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, WinAc
                 if (a < np && bb < np) A.fim[a * NP + bb] += w * (lam * g[a] * g[bb]);
     }
     if (S.use_rer) {
+        // dep[j]: the parameters reaction j reads.  For the others a perturbation
+        // of c_k leaves lam'_j = lam_j, and their term lam log 1 - lam + lam is
+        // exactly +0, so skipping them changes no bit of the sum.
 #pragma unroll
         for (int kp = 0; kp < NP; ++kp) {
             if (kp >= np) continue;
@@ -155,6 +159,7 @@ __device__ void fim_rer_point(const SNet& S, const int (&x)[NS], double w, WinAc
             for (int p = 0; p < kMaxP; ++p) cv[p] = (p == kp) ? S.ceps[p] : S.c[p];
             double h = 0.0;
             for (int j = 0; j < S.m; ++j) {
+                if (!((dep[j] >> kp) & 1u)) continue;
                 const double lam = lamv[j];
                 const double lp = prop_with<NS>(S, j, x, cv);
                 if (lam > 0.0) h += lam * log(lam / lp) - lam + lp;
@@ -175,8 +180,26 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
     const DevInst* I = insts + blockIdx.x;
     const bool small = I->net.n_species <= 2 && I->net.n_params <= 4;
     if (small != (NS <= 2)) return;  // the other launch's instance
+    __shared__ uint32_t dep[kMaxM];
     const int tid = threadIdx.x;
-    if (tid == 0) load_net(S, I);
+    if (tid == 0) {
+        load_net(S, I);
+        for (int j = 0; j < kMaxM; ++j) {
+            uint32_t d = 0;
+            if (j < S.m) {
+                if (S.rate_param[j] >= 0) d |= 1u << S.rate_param[j];
+                for (int f = 0; f < S.nf[j]; ++f) {
+                    const int kind = S.fkind[j][f];
+                    if (kind == PARREP_PARAM || kind == PARREP_HILL_REP ||
+                        kind == PARREP_HILL_SWITCH)
+                        d |= 1u << S.fhp[j][f];
+                    if (kind == PARREP_HILL_SWITCH)
+                        d |= (1u << S.fp2[j][f]) | (1u << S.fp3[j][f]);
+                }
+            }
+            dep[j] = d;
+        }
+    }
     for (int i = tid; i < kAccLen; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
     WinAcc<NP> A;
@@ -201,7 +224,7 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
         int x[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) x[i] = S.hist_lo[i] + (int)((idx / stride[i]) % nb[i]);
-        fim_rer_point<NS, NP>(S, x, h, A);
+        fim_rer_point<NS, NP>(S, dep, x, h, A);
     }
     // states outside the box: their window time sits in the spill table
     for (int i = tid; i < kSpillCap; i += blockDim.x) {
@@ -210,7 +233,7 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
         int x[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) x[s] = (int)((sl.key >> (15 * s)) & 0x7FFF);
-        fim_rer_point<NS, NP>(S, x, sl.w, A);
+        fim_rer_point<NS, NP>(S, dep, x, sl.w, A);
     }
     const int np = S.np;
     const bool lead = (tid & 63) == 0;
