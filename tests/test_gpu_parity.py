@@ -228,14 +228,17 @@ def test_parallel_hook(B, oracle):
 
 
 def test_full_size_toggle_sampled(B, oracle):
-    """Toggle Omega=50, R=1024, T=2e4 (the benchmark workload) in the launch
-    shape the benchmark uses; one sampled instance against the oracle, and
+    """Toggle Omega=50, R=1024, T=2e4 (the benchmark workload) run the way the
+    benchmark runs it: a plan with 4 replicas per lane and 4 waves, executed
+    with parrep_plan_run; one sampled instance against the oracle, and
     properties that hold for every instance."""
     import torch
     probs = [W.c2_toggle(seed=0, instance_id=i) for i in range(4)]
     _flush("full-size toggle batch of %d" % len(probs))
-    outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+    plan = B.Plan(probs, replicas_per_lane=4, waves=4)
+    plan.run()
     torch.cuda.synchronize()
+    outs = plan.outputs
     hs = [o.to_host() for o in outs]
     for p, h in zip(probs, hs):
         assert h.T_s == p.T
@@ -248,6 +251,7 @@ def test_full_size_toggle_sampled(B, oracle):
         hs[0].cycle_log = None
         o.cycle_log = None
         assert_same(o, hs[0], what="full-size")
+    plan.close()
 
 
 def _gs(i, V=240.0, **kw):
