@@ -190,3 +190,34 @@ def test_paper_genetic_switch_speedup_vs_replicas(B):
         print("R=%3d: speedup %.1f (cycles %d)" % (R, sp[R], c[4]), flush=True)
     assert sp[20] < sp[50] < sp[100]
     assert sp[100] > 3.0
+
+
+def test_genetic_switch_accuracy_vs_thresholds(B):
+    """ParRep is exact only as the decorrelation and dephasing thresholds grow
+    (Sec. II B); the genetic switch needs large ones (Sec. IV B).  The
+    stationary mean protein count, from 250 trajectories of T = 1e5 (burn-in
+    T/2, R = 100), against the exact generator value: with n_c = n_p = 5e3
+    the replicas leave the low well long before they reach its
+    quasi-stationary law and the mean is far too low; with 1e5 it agrees to
+    four standard errors."""
+    import torch
+    N, T = 250, 1e5
+    c = W.genetic_switch_c(2400.0)
+    L, Q, pi = E.genetic_switch_pi(c, 14, 3300)
+    exact = float(pi @ L.states()[2])
+    dev = {}
+    for n in (5e3, 1e5):
+        probs = [W.genetic_switch_problem(seed=11, instance_id=i, T=T, n_c=n, n_p=n)
+                 for i in range(N)]
+        outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+        torch.cuda.synchronize()
+        hs = [o.to_host() for o in outs]
+        assert [h.T_s for h in hs] == [T] * N
+        assert [h.counters["spill_overflow"] for h in hs] == [0] * N
+        y = np.array([h.y[3] for h in hs]) / (T / 2)  # time-averaged protein over the window
+        se = y.std(ddof=1) / math.sqrt(N)
+        dev[n] = (y.mean() - exact, se)
+        print("n_c = n_p = %g: mean protein %.2f +- %.2f (exact %.2f)" % (n, y.mean(), se, exact),
+              flush=True)
+    assert dev[5e3][0] < -0.3 * exact
+    assert abs(dev[1e5][0]) < 4 * dev[1e5][1]
