@@ -238,6 +238,10 @@ def main():
                     help="skip the large single run (R = 65536) in the forms section")
     ap.add_argument("--phase-clock", action="store_true",
                     help="report where each trajectory's workgroup spent its time")
+    ap.add_argument("--workload", choices=("toggle", "genetic_switch"), default="toggle",
+                    help="genetic_switch: the general kernels on Sec. IV B's network (V = 2400, "
+                         "R = 100, n_c = n_p = 2e4); no roofline (latency-bound at the paper's "
+                         "batch of 100 trajectories)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -260,9 +264,14 @@ def main():
         sys.exit(1)
     B.lib()
     ctx = B.context(0)
-    probs = [W.c2_toggle(seed=0, instance_id=i, T=args.T) for i in range(args.instances)]
+    toggle = args.workload == "toggle"
+    if toggle:
+        probs = [W.c2_toggle(seed=0, instance_id=i, T=args.T) for i in range(args.instances)]
+    else:
+        probs = [W.genetic_switch_problem(seed=0, instance_id=i, T=args.T)
+                 for i in range(args.instances)]
     shape = None
-    if args.rpl == 0 and args.waves == 0 and not args.no_autotune:
+    if toggle and args.rpl == 0 and args.waves == 0 and not args.no_autotune:
         # untimed: pick the launch shape for R = 1024 on copies cut to 2e6 events
         t = time.perf_counter()
         shape = B.parrep_autotune(probs[0].replace(instance_id=1 << 30), instances=1024,
@@ -325,20 +334,24 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "toggle switch Omega=50 (a1=a2=3, beta=gamma=2), R=1024, "
-                        "t_c=t_p=20, T=%g, burn-in T/2, hist [0,400]^2, FIM+RER(a1,a2,beta,gamma); "
-                        "%d independent trajectories per step" % (args.T, args.instances),
+            "workload": ("toggle switch Omega=50 (a1=a2=3, beta=gamma=2), R=1024, "
+                         "t_c=t_p=20, T=%g, burn-in T/2, hist [0,400]^2, FIM+RER(a1,a2,beta,gamma); "
+                         "%d independent trajectories per step" % (args.T, args.instances)
+                         if toggle else
+                         "genetic switch V=2400, R=100, n_c=n_p=2e4 transitions, T=%g, burn-in "
+                         "T/2, FIM+RER of 8 parameters; %d independent trajectories per step"
+                         % (args.T, args.instances)),
             "instances": args.instances,
             "launch_shape": ({"replicas_per_lane": shape[0], "waves": shape[1], "autotuned": True}
                              if shape else {"replicas_per_lane": args.rpl, "waves": args.waves}),
-            "replicas": 1024,
+            "replicas": probs[0].R,
             "horizon": args.T,
         },
         "solves_per_s": args.instances / (wall / args.steps),
         "events_per_step": ev,
         "events_by_phase": per_phase,
         "all_runs_reached_T": ok,
-        "roofline": {
+        "roofline": None if not toggle else {
             "bound": "alu",
             "kernel": "k_instance",
             "achieved": achieved / 1e12,
