@@ -193,3 +193,37 @@ def test_time_mode_dephasing_rounds(oracle):
         _, n = oracle.dephase(p.replace(dephase=tp), (12, 3))
         rounds.append(n)
     assert rounds[0] == 0 and 0 < rounds[1] < rounds[2]
+
+
+def _self_repressor():
+    # 0 -> X at c0 / (1 + (x / 5) ** c2), X -> 0 at c1 x: a birth-death chain
+    # whose Hill exponent is a parameter, here not an integer
+    return W.Network(
+        name="self_repressor", n_species=1, n_params=3, param_names=("k", "gamma", "n"),
+        reactions=(
+            W.Reaction(0, 1.0, (W.Factor(W.HILL_REP, 0, K=5.0, hill_param=2),), (1,)),
+            W.Reaction(1, 1.0, (W.Factor(W.FALLING, 0, order=1),), (-1,)),
+        ))
+
+
+def _repressor_pi(c, N):
+    x = np.arange(N + 1, dtype=np.float64)
+    return E.birth_death_pi(c[0] / (1.0 + (x / 5.0) ** c[2]), c[1] * x)
+
+
+def test_ssa_law_non_integral_hill_exponent(oracle):
+    """The GPU takes integral Hill exponents only; the oracle also evaluates
+    non-integral ones.  Pinned by the product-form stationary law of the
+    birth-death chain (Sec. I A's generator with one species): exponent 2.5
+    matches, while exponents 2.3 and 2.7 (and the integers around 2.5) are
+    rejected by the same statistic."""
+    c = (40.0, 1.0, 2.5)
+    p = W.Problem(net=_self_repressor(), c=c, x0=(0,), region_w=(1,), region_theta=1000, R=4,
+                  decorr_mode=W.STEPS, decorr=1e18, T=1e5, t_burn=1e3, hist_lo=(0,),
+                  hist_hi=(60,), rer_eps=None, seed=3)
+    r = oracle.run(p)
+    assert r.counters["cycles"] == 0 and r.outside == 0.0
+    h = r.hist / r.hist.sum()
+    assert E.tv(h, _repressor_pi(c, 60)) < 0.006
+    for n in (2.0, 2.3, 2.7, 3.0):
+        assert E.tv(h, _repressor_pi((c[0], c[1], n), 60)) > 0.035, n
