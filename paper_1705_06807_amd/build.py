@@ -44,7 +44,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
         jobs.append((inst, "parrep_instance_ns%d_w%d.o" % (ns, w),
                      ["-DPARREP_NS=%d" % ns, "-DPARREP_WAVES=%d" % w]))
     deps = srcs + [inst, os.path.join(CSRC, "parrep_internal.h"), os.path.join(CSRC, "parrep_host.h"),
-                   os.path.join(CSRC, "parrep_neglog.h"),
+                   os.path.join(CSRC, "parrep_neglog.h"), os.path.join(CSRC, "parrep_fx.h"),
                    os.path.join(CSRC, "parrep_device.h"), os.path.join(ROOT, "include", "parrep.h")]
     if not force and os.path.exists(LIB):
         if os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):

@@ -24,6 +24,7 @@
 //     holding times (each truncated to 2^-64), so the burn-in time and the
 //     horizon are crossed at one event whatever the reduction order.
 #pragma once
+#include "parrep_fx.h"
 #include "parrep_internal.h"
 #include "parrep_neglog.h"
 
@@ -117,55 +118,6 @@ __device__ __forceinline__ double u_sel(const Blk& b) {
 __device__ __forceinline__ double neglog_u_open(const Blk& b, const double* __restrict__ lt) {
     const uint64_t w = ((uint64_t)b.w1 << 32) | b.w0;
     return neglog_u53((w >> 11) + 1, lt);
-}
-
-// ---------------------------------------------------------------------------
-// 64.64 fixed-point clock
-// ---------------------------------------------------------------------------
-struct Fx {
-    uint64_t hi, lo;
-};
-
-__device__ __forceinline__ Fx fx_add(Fx a, Fx b) {
-    Fx r;
-    r.lo = a.lo + b.lo;
-    r.hi = a.hi + b.hi + (r.lo < a.lo ? 1u : 0u);
-    return r;
-}
-__device__ __forceinline__ Fx fx_sub(Fx a, Fx b) {
-    Fx r;
-    r.lo = a.lo - b.lo;
-    r.hi = a.hi - b.hi - (a.lo < b.lo ? 1u : 0u);
-    return r;
-}
-__device__ __forceinline__ bool fx_ge(Fx a, Fx b) {
-    return a.hi > b.hi || (a.hi == b.hi && a.lo >= b.lo);
-}
-__device__ __forceinline__ bool fx_gt(Fx a, Fx b) { return !fx_ge(b, a); }
-
-// Correctly rounded uint64 -> double: both halves are exact, one rounding in the sum.
-__device__ __forceinline__ double u64_to_f64(uint64_t v) {
-    return (double)(uint32_t)(v >> 32) * 0x1.0p32 + (double)(uint32_t)v;
-}
-__device__ __forceinline__ double fx_to_f64(Fx v) {
-    return u64_to_f64(v.hi) + u64_to_f64(v.lo) * 0x1.0p-64;
-}
-
-// floor(d * 2^64) for 0 <= d < 2^52, by exact steps; +inf and larger saturate.
-__device__ __forceinline__ Fx fx_from(double d) {
-    if (!(d < 0x1.0p52)) return Fx{1ull << 52, 0};
-    if (!(d > 0.0)) return Fx{0, 0};
-    const double ip = floor(d);
-    const double a = (d - ip) * 0x1.0p32;
-    const double ah = floor(a);
-    const double b = (a - ah) * 0x1.0p32;
-    const double bl = floor(b);
-    const double iph = floor(ip * 0x1.0p-32);
-    const double ipl = ip - iph * 0x1.0p32;
-    Fx r;
-    r.hi = ((uint64_t)(uint32_t)iph << 32) | (uint64_t)(uint32_t)ipl;
-    r.lo = ((uint64_t)(uint32_t)ah << 32) | (uint64_t)(uint32_t)bl;
-    return r;
 }
 
 // Values known to be equal in all lanes, moved to scalar registers.
@@ -862,7 +814,7 @@ __device__ __forceinline__ void block_min_sum(Shared<E, WAVES>& sh, int& par, in
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         vmin = min(vmin, __shfl_xor(vmin, off));
-        vsum = fx_add(vsum, shfl_xor_fx(vsum, off));
+        vsum = fx_add_sat(vsum, shfl_xor_fx(vsum, off));
     }
     if (WAVES == 1) {
         omin = vmin;
@@ -882,7 +834,7 @@ __device__ __forceinline__ void block_min_sum(Shared<E, WAVES>& sh, int& par, in
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
         omin = min(omin, sh.wmin[p][w]);
-        osum = fx_add(osum, Fx{sh.wsum[p][w][0], sh.wsum[p][w][1]});
+        osum = fx_add_sat(osum, Fx{sh.wsum[p][w][0], sh.wsum[p][w][1]});
     }
 }
 
@@ -1391,7 +1343,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                     for (int i = 0; i < NS; ++i) post[i] = Y[k][i];
                     apply_dx<NS>(post, dxk[k]);
                     if (region_hot<NS, M>(hn, post) != W && lfirst == INT_MAX) lfirst = r;
-                    lsum = fx_add(lsum, fx_from(tauk[k]));
+                    lsum = fx_add_sat(lsum, fx_from(tauk[k]));
                 }
             }
             int first;
@@ -1407,7 +1359,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
 #pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
-                    if (r < K) l2 = fx_add(l2, fx_from(tauk[k]));
+                    if (r < K) l2 = fx_add_sat(l2, fx_from(tauk[k]));
                 }
                 int dummy;
                 block_min_sum<E, WAVES>(sh, par, wid, lane, INT_MAX, l2, dummy, total);
@@ -1565,7 +1517,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         cn[PARREP_CNT_CYCLES] = rs.c_cycles;
         cn[PARREP_CNT_S3_ROUNDS] = rs.c_s3;
         cn[PARREP_CNT_S2_ROUNDS] = rs.c_s2;
-        cn[PARREP_CNT_STATUS] = rs.end_phase == 9 ? 1 : 0;
+        cn[PARREP_CNT_STATUS] = rs.end_phase == 9 ? PARREP_RUN_BUDGET : PARREP_RUN_OK;
         cn[PARREP_CNT_FV_RESTARTS] = rs.c_fv;
         cn[PARREP_CNT_END_PHASE] = rs.end_phase;
         cn[PARREP_CNT_N_CYCLE_LOG] = rs.n_log;

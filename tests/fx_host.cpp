@@ -1,0 +1,26 @@
+// Host build of the device's 64.64 fixed-point clock, for its test: reads
+// doubles (hex floats, one per line) and prints, for each, floor(d 2^64) as
+// "hi lo" (hex); then the plain and the saturating sums of all of them, in
+// input order, as "plain hi lo" and "sat hi lo".
+#define PARREP_HD
+#include "../paper_1705_06807_amd/csrc/parrep_fx.h"
+
+#include <cinttypes>
+#include <cstdio>
+#include <cstdlib>
+
+int main() {
+    using namespace parrep;
+    char buf[128];
+    Fx plain{0, 0}, sat{0, 0};
+    while (std::fgets(buf, sizeof buf, stdin)) {
+        const double d = std::strtod(buf, nullptr);
+        const Fx v = fx_from(d);
+        std::printf("%" PRIx64 " %" PRIx64 "\n", v.hi, v.lo);
+        plain = fx_add(plain, v);
+        sat = fx_add_sat(sat, v);
+    }
+    std::printf("plain %" PRIx64 " %" PRIx64 "\n", plain.hi, plain.lo);
+    std::printf("sat %" PRIx64 " %" PRIx64 "\n", sat.hi, sat.lo);
+    return 0;
+}
