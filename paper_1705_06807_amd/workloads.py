@@ -257,6 +257,56 @@ def birth_death(kb: float = 1.0) -> Network:
     )
 
 
+def self_loop() -> Network:
+    """One channel that fires at the constant rate c1 and changes nothing:
+    every holding time is Exp(c1) and the state never moves."""
+    return Network(
+        name="self_loop",
+        n_species=1,
+        n_params=1,
+        param_names=("c1",),
+        reactions=(Reaction(0, 1.0, (), (0,)),),
+    )
+
+
+def flip_chain() -> Network:
+    """Two species with x + y = 1: a self-loop at rate c1, and y -> x, x -> y
+    at rate c2 each (so a0 = c1 + c2 in both states).  With the sets
+    {x >= 1} and {x < 1}, every jump leaves the current set with probability
+    c2 / (c1 + c2), independently of the holding times."""
+    return Network(
+        name="flip_chain",
+        n_species=2,
+        n_params=2,
+        param_names=("c1", "c2"),
+        reactions=(
+            Reaction(0, 1.0, (), (0, 0)),
+            Reaction(1, 1.0, (Factor(FALLING, 1, order=1),), (1, -1)),
+            Reaction(1, 1.0, (Factor(FALLING, 0, order=1),), (-1, 1)),
+        ),
+    )
+
+
+def self_loop_problem(seed: int = 0, instance_id: int = 0, rate: float = 4.0, R: int = 16,
+                      t_p: float = 2.5) -> Problem:
+    """Dephasing-rule pin: constant a0 = rate and one set containing every
+    state, so no replica ever leaves it (no Fleming-Viot restart)."""
+    return Problem(
+        net=self_loop(), c=(rate,), x0=(0,), region_w=(0,), region_theta=0, R=R,
+        decorr_mode=TIME, decorr=0.0, dephase_mode=TIME, dephase=t_p, T=1e6, t_burn=0.0,
+        hist_lo=(0,), hist_hi=(0,), rer_eps=None, seed=seed, instance_id=instance_id)
+
+
+def flip_chain_problem(seed: int = 0, instance_id: int = 0, c1: float = 3.0, c2: float = 1.0,
+                       t_c: float = 1.0, R: int = 1, T: float = 2e4) -> Problem:
+    """Decorrelation-rule pin: the flip chain from (1, 0) with sets {x >= 1}
+    and {x < 1}, TIME decorrelation t_c and no dephasing rounds."""
+    return Problem(
+        net=flip_chain(), c=(c1, c2), x0=(1, 0), region_w=(1, 0), region_theta=1, R=R,
+        decorr_mode=TIME, decorr=t_c, dephase_mode=STEPS, dephase=0.0, T=T, t_burn=T / 2.0,
+        hist_lo=(0, 0), hist_hi=(1, 1), rer_eps=None, seed=seed, instance_id=instance_id)
+
+
 # --------------------------------------------------------------------------
 # Problems at the benchmark configurations
 # --------------------------------------------------------------------------

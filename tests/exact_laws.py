@@ -369,3 +369,50 @@ def genetic_switch_fim_integrand(xi, x1, x2, c):
         w = np.where(l > 0, 1.0 / np.where(l > 0, l, 1.0), 0.0)
         out += np.einsum("as,bs,s->sab", d[:, j], d[:, j], w)
     return out
+
+
+# --------------------------------------------------------------------------
+# Exact laws of the time-mode stopping rules of Alg. 1 (decorrelation and
+# dephasing), on chains whose total rate a0 is the same in every state, so
+# that the holding times are iid Exp(a0) and independent of the jump chain.
+# --------------------------------------------------------------------------
+
+def dephase_rounds_cdf(a0: float, t_p: float, R: int, n_max: int) -> np.ndarray:
+    """P(N <= n), n = 0..n_max, for the number N of dephasing rounds when no
+    replica ever leaves the set: replica r is done after the first round n_r
+    at which its own elapsed time (a sum of n_r iid Exp(a0)) reaches t_p, and
+    the step stops after the first round at which every replica is done, so
+    N = max_r n_r with P(n_r <= n) = P(Poisson(a0 t_p) <= n - 1)."""
+    from scipy import stats
+    n = np.arange(n_max + 1)
+    single = np.where(n >= 1, stats.poisson(a0 * t_p).cdf(n - 1), 0.0)
+    return single ** R
+
+
+def decorr_events_pmf(a0: float, p_flip: float, t_c: float, k_max: int) -> np.ndarray:
+    """P(K = k), k = 0..k_max, for the number K of decorrelation events when
+    every jump leaves the current set with probability p_flip, independently
+    of the holding times (iid Exp(a0)).  Time in the current set grows by the
+    holding time of each jump that stays in it and restarts at 0 on a jump
+    that leaves it; the step ends at the first jump after which it is >= t_c.
+
+    Renewal: an attempt starts with time 0 in a set.  With M the number of
+    in-set jumps whose holding times first reach t_c (P(M = m) =
+    P(Poisson(a0 t_c) = m - 1)), it succeeds after m jumps with probability
+    P(M = m) q^m (q = 1 - p_flip), or fails at jump j (the first j - 1 stay,
+    the j-th leaves) with probability P(M >= j) q^(j-1) p_flip.  K is the sum
+    of the failed attempts' lengths and the successful one's:
+    f = g + h * f (discrete convolution)."""
+    from scipy import stats
+    q = 1.0 - p_flip
+    k = np.arange(k_max + 1)
+    pois = stats.poisson(a0 * t_c)
+    pm = np.where(k >= 1, pois.pmf(k - 1), 0.0)        # P(M = k)
+    p_ge = np.where(k >= 1, pois.sf(k - 2), 0.0)       # P(M >= k) = P(Poisson >= k - 1)
+    p_ge[1] = 1.0
+    g = pm * q ** k
+    h = np.where(k >= 1, p_ge * q ** np.maximum(k - 1, 0) * p_flip, 0.0)
+    f = np.zeros(k_max + 1)
+    for kk in range(1, k_max + 1):
+        f[kk] = g[kk] + np.dot(h[1:kk], f[kk - 1:0:-1])
+    return f

@@ -184,6 +184,27 @@ def test_absorbing_state(B, oracle):
         assert_same(oracle.run(q, cycle_log_cap=4096), _gpu_run(B, q), what="absorbing")
 
 
+@pytest.mark.parametrize("R", [4096, 8192, 65536])
+def test_absorbing_replicas_reach_the_horizon(B, oracle, R):
+    # Decorrelation ends on the jump into the absorbing state x = 0, so every
+    # replica of the parallel step holds there with tau = +inf.  Each enters
+    # the round's clock sum as 2^52; a multiple of 4096 of them must still
+    # end the run at the horizon (the fixed-point replica sums saturate).
+    # The event budget bounds the run had the horizon been missed.
+    p = W.Problem(net=W.pure_death(), c=(1.0,), x0=(1,), region_w=(1,), region_theta=3, R=R,
+                  decorr_mode=W.STEPS, decorr=1, dephase_mode=W.STEPS, dephase=2, T=50.0,
+                  t_burn=25.0, hist_lo=(0,), hist_hi=(10,), rer_eps=None,
+                  max_events=64 * R)
+    for i in range(3):
+        q = p.replace(instance_id=i)
+        _flush("absorbing R=%d instance %d" % (R, i))
+        o = oracle.run(q, cycle_log_cap=4096)
+        assert o.counters["status"] == 0 and o.counters["end_phase"] == 3
+        g = _gpu_run(B, q)
+        assert_same(o, g, what="absorbing R=%d" % R)
+        assert g.T_s == 50.0
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (4, 1), (16, 1), (1, 4), (4, 4), (16, 4), (1, 16),
                                    (4, 16), (16, 16), (64, 16)])
 def test_launch_shapes_agree(B, oracle, shape):
@@ -213,6 +234,33 @@ def test_dephase_hook(B, oracle):
         Yg, ng = B.parrep_dephase_only(p, (12, 3), cycle=7)
         Yo, no = oracle.dephase(p, (12, 3), cycle=7)
         assert ng == no and np.array_equal(Yg, Yo), R
+
+
+@pytest.mark.parametrize("R", [1, 16, 256, 4096])
+def test_time_mode_dephasing_stop_hook(B, oracle, R):
+    # the chain of the oracle's dephasing stop-rule pin (constant a0, one set):
+    # the device stops after the same round as the oracle, whose round count
+    # follows the exact law P(N <= n) = P(Poisson(a0 t_p) <= n - 1)^R
+    for i in range(40 if R < 4096 else 8):
+        p = W.self_loop_problem(seed=R, instance_id=i, R=R)
+        _flush("self-loop dephasing R=%d instance %d" % (R, i))
+        Yg, ng = B.parrep_dephase_only(p, (0,), cycle=i % 7)
+        Yo, no = oracle.dephase(p, (0,), cycle=i % 7)
+        assert ng == no and np.array_equal(Yg, Yo), (R, i, ng, no)
+
+
+@pytest.mark.parametrize("R", [1, 64])
+def test_time_mode_decorrelation_stop_parity(B, oracle, R):
+    # the chain of the oracle's decorrelation stop-rule pin: thousands of
+    # cycles, each decorrelation ended by the time-in-set rule; the cycle
+    # records (decorrelation events per cycle among them) must be equal
+    for i in range(2):
+        p = W.flip_chain_problem(seed=5, instance_id=i, R=R, T=2000.0)
+        _flush("flip chain R=%d instance %d" % (R, i))
+        o = oracle.run(p, cycle_log_cap=8192)
+        assert 100 < o.counters["n_cycle_log"] <= 8192
+        g = _gpu_run(B, p, cycle_log_cap=8192)
+        assert_same(o, g, what="flip chain R=%d" % R)
 
 
 def test_parallel_hook(B, oracle):

@@ -227,3 +227,106 @@ def test_ssa_law_non_integral_hill_exponent(oracle):
     assert E.tv(h, _repressor_pi(c, 60)) < 0.006
     for n in (2.0, 2.3, 2.7, 3.0):
         assert E.tv(h, _repressor_pi((c[0], c[1], n), 60)) > 0.035, n
+
+
+def _chi2_ok(counts, probs, min_expected=5.0, q=1e-4):
+    """Chi-square goodness of fit with adjacent cells merged until each
+    expects at least min_expected; True when the fit is not rejected at
+    level q."""
+    n = counts.sum()
+    cells_o, cells_e = [], []
+    acc_o = acc_e = 0.0
+    for o, p in zip(counts, probs):
+        acc_o += o
+        acc_e += p * n
+        if acc_e >= min_expected:
+            cells_o.append(acc_o)
+            cells_e.append(acc_e)
+            acc_o = acc_e = 0.0
+    if acc_e > 0 or acc_o > 0:
+        cells_o[-1] += acc_o
+        cells_e[-1] += acc_e
+    o = np.array(cells_o)
+    e = np.array(cells_e)
+    chi2 = ((o - e) ** 2 / e).sum()
+    return chi2 < stats.chi2(len(o) - 1).ppf(1.0 - q), chi2, len(o)
+
+
+@pytest.mark.parametrize("R", [1, 16, 256])
+def test_time_mode_dephasing_stop_law(oracle, R):
+    """Dephasing in time mode stops after the first round at which every
+    replica's own elapsed time has reached t_p (Alg. 1, dephasing step).
+    With a constant total rate a0 and one set holding every state, no
+    replica restarts, each replica's elapsed time after n rounds is a sum of
+    n iid Exp(a0), and the round count N = max_r n_r follows
+    P(N <= n) = P(Poisson(a0 t_p) <= n - 1)^R exactly.  Stopping on the
+    largest elapsed time instead (N = min_r n_r), or one round early or
+    late, is rejected at R = 16 and 256."""
+    a0, t_p = 4.0, 2.5
+    n_samp = 3000 if R < 256 else 1500
+    rounds = np.empty(n_samp, dtype=np.int64)
+    for i in range(n_samp):
+        p = W.self_loop_problem(seed=R, instance_id=i, rate=a0, R=R, t_p=t_p)
+        Y, n = oracle.dephase(p, (0,), cycle=i % 7)
+        assert (Y == 0).all()
+        rounds[i] = n
+    n_max = int(rounds.max()) + 40
+    cdf = E.dephase_rounds_cdf(a0, t_p, R, n_max)
+    pmf = np.diff(np.concatenate([[0.0], cdf]))
+    counts = np.bincount(rounds, minlength=n_max + 1)[:n_max + 1].astype(float)
+    ok, chi2, cells = _chi2_ok(counts, pmf)
+    assert ok, (chi2, cells)
+    if R > 1:
+        # the same statistic rejects the plausible misreadings
+        cdf_min = 1.0 - (1.0 - E.dephase_rounds_cdf(a0, t_p, 1, n_max)) ** R
+        for wrong in (cdf_min, np.concatenate([[0.0], cdf[:-1]]), np.concatenate([cdf[1:], [1.0]])):
+            pw = np.clip(np.diff(np.concatenate([[0.0], wrong])), 1e-300, None)
+            assert not _chi2_ok(counts, pw)[0]
+
+
+def test_time_mode_decorrelation_stop_law(oracle):
+    """Decorrelation in time mode ends at the first jump after which the
+    process has spent t_c in its current set without interruption; leaving
+    the set makes the new set current and restarts the time (Alg. 1,
+    decorrelation step).  On the flip chain every jump leaves the set with
+    probability p = c2/(c1+c2) and the holding times are iid Exp(c1+c2), so
+    the number of decorrelation events per cycle has the renewal law of
+    decorr_events_pmf.  Not restarting the time on leaving the set, or also
+    counting the holding time of the jump that leaves it, gives other laws
+    that the same statistic rejects."""
+    c1, c2, t_c = 3.0, 1.0, 1.0
+    a0, pf = c1 + c2, c2 / (c1 + c2)
+    s1 = []
+    for seed in range(3):
+        r = oracle.run(W.flip_chain_problem(seed=seed, c1=c1, c2=c2, t_c=t_c, T=2e4),
+                       cycle_log_cap=40000)
+        log = r.cycle_log
+        assert r.counters["n_cycle_log"] <= 40000 and len(log) > 3000
+        s1.extend(int(v) for v in log[:-1, 1])  # the last cycle is cut by the horizon
+    s1 = np.array(s1)
+    k_max = int(s1.max()) + 60
+    pmf = E.decorr_events_pmf(a0, pf, t_c, k_max)
+    counts = np.bincount(s1, minlength=k_max + 1)[:k_max + 1].astype(float)
+    ok, chi2, cells = _chi2_ok(counts, pmf)
+    assert ok, (chi2, cells)
+    # no restart: K = jumps until the in-set holding times alone reach t_c
+    rng = np.random.default_rng(0)
+    no_reset = []
+    with_exit_time = []
+    for _ in range(40000):
+        e, k = 0.0, 0
+        while not e >= t_c:
+            tau = rng.exponential(1.0 / a0)
+            k += 1
+            if rng.random() >= pf:
+                e += tau
+        no_reset.append(k)
+        e, k = 0.0, 0
+        while not e >= t_c:
+            tau = rng.exponential(1.0 / a0)
+            k += 1
+            e = tau if rng.random() < pf else e + tau
+        with_exit_time.append(k)
+    for wrong in (no_reset, with_exit_time):
+        pw = np.bincount(np.array(wrong), minlength=k_max + 1)[:k_max + 1] / len(wrong)
+        assert not _chi2_ok(counts, np.clip(pw, 1e-12, None))[0]
