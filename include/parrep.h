@@ -51,7 +51,8 @@ typedef enum {
     PARREP_EDEVICE = -3,      /* a HIP call failed                              */
     PARREP_EUNSUPPORTED = -4, /* valid input the library does not handle       */
     PARREP_EBUSY = -5,        /* result not ready yet (server poll)             */
-    PARREP_ECANCELLED = -6    /* request was cancelled                          */
+    PARREP_ECANCELLED = -6,   /* request was cancelled                          */
+    PARREP_EOVERFLOW = -7     /* a run's spill table overflowed (see counters) */
 } parrep_status;
 
 /* Propensity factor kinds.  A reaction's propensity (Sec. I A) is
@@ -80,13 +81,25 @@ enum {
     PARREP_CNT_CYCLES = 4,           /* parallel steps that ended with an exit     */
     PARREP_CNT_S3_ROUNDS = 5,
     PARREP_CNT_S2_ROUNDS = 6,
-    PARREP_CNT_STATUS = 7,           /* 0 horizon reached, 1 event budget hit, 2 aborted */
+    PARREP_CNT_STATUS = 7,           /* a PARREP_RUN_* value                       */
     PARREP_CNT_FV_RESTARTS = 8,
     PARREP_CNT_END_PHASE = 9,        /* 1 horizon in decorrelation, 3 in parallel step, 9 stopped */
     PARREP_CNT_N_CYCLE_LOG = 10,     /* cycle records produced (may exceed the capacity) */
     PARREP_CNT_SPILL_OVERFLOW = 11   /* credited events outside the histogram box whose state
                                         found no spill slot (their time is in the outside
                                         totals but not in FIM/RER/Y); 0 in normal runs */
+};
+
+/* counters[PARREP_CNT_STATUS] of a result.  Solves run asynchronously, so a
+ * run that cannot complete its outputs reports it here (and a served request
+ * through parrep_server_poll's status), not through the return value. */
+enum {
+    PARREP_RUN_OK = 0,             /* the clock reached the horizon                   */
+    PARREP_RUN_BUDGET = 1,         /* the event budget stopped the run first           */
+    PARREP_RUN_SPILL_OVERFLOW = 3  /* the horizon was reached, but time at states
+                                      outside the histogram box found no spill slot:
+                                      FIM, RER and Y miss it (PARREP_CNT_SPILL_OVERFLOW
+                                      counts those credits)                           */
 };
 
 /* stats[] layout of a result (PARREP_NSTATS doubles) */

@@ -264,6 +264,10 @@ __global__ void __launch_bounds__(256) k_finalize(const DevInst* __restrict__ in
         for (int a = 0; a < np * np; ++a) I->stats[PARREP_ST_FIM + a] = acc[kAccFim + a] / win;
         for (int a = 0; a < np; ++a) I->stats[PARREP_ST_RER + a] = acc[kAccRer + a] / win;
         for (int i = 0; i < S.n; ++i) I->stats[PARREP_ST_Y + i] = acc[kAccY + i];
+        // time at a state that found no spill slot is missing from FIM, RER
+        // and Y: the run reports it in its status
+        if (I->counters[PARREP_CNT_SPILL_OVERFLOW] != 0 && I->counters[PARREP_CNT_STATUS] == 0)
+            I->counters[PARREP_CNT_STATUS] = PARREP_RUN_SPILL_OVERFLOW;
     }
 }
 

@@ -454,13 +454,16 @@ int parrep_server_poll(parrep_server* s, uint64_t ticket, const parrep_result* r
         s->cv_done.wait(lk, [&] { return r->state == Req::DONE || r->state == Req::FAILED; });
     }
     int rc = r->status;
+    // a run whose spill table overflowed left time out of FIM, RER and Y:
+    // the pooled outputs are written, and the request reports the overflow
+    const bool overflow = rc == PARREP_OK && r->counters[PARREP_CNT_STATUS] == PARREP_RUN_SPILL_OVERFLOW;
     if (r->inflight > 0) {  // failed with runs still in flight: reaped when they finish
         r->forgotten = true;
         return rc;
     }
     if (info) {
         info->runs = r->done;
-        info->status = r->status;
+        info->status = overflow ? PARREP_EOVERFLOW : r->status;
         info->rse = r->rse;
         info->events = r->events;
         info->latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
@@ -507,6 +510,9 @@ int parrep_server_poll(parrep_server* s, uint64_t ticket, const parrep_result* r
     s->reqs.erase(ticket);
     release_pool(s, *r);
     delete r;
+    if (rc == PARREP_OK && overflow)
+        rc = fail(PARREP_EOVERFLOW, "a run's spill table overflowed: FIM, RER and window "
+                                    "integrals miss time outside the histogram box");
     return rc;
 }
 

@@ -98,3 +98,34 @@ def test_net_of_another_context_rejected(B):
 
 def test_empty_batch_rejected(B):
     assert _code(B, lambda: B.parrep_solve_batch([])) == EINVAL
+
+
+def test_spill_overflow_is_reported(B):
+    """Time at states outside the histogram box goes to a 2048-slot spill
+    table per run; a run that visits more distinct outside states cannot
+    keep their FIM, RER and window-integral terms, and says so: its status
+    counter is PARREP_RUN_SPILL_OVERFLOW (3), and a served request that
+    pools such a run fails with PARREP_EOVERFLOW (-7), its outputs written."""
+    import torch
+    # toggle at Omega = 150 visits ~10^4 distinct states in T = 300; a box
+    # of one state leaves them all to the spill table
+    p = W.c4_toggle(seed=1, R=64, T=300.0, t_cp=1.0).replace(hist_hi=(0, 0))
+    g = B.parrep_solve(p, cycle_log_cap=0)
+    torch.cuda.synchronize()
+    h = g.to_host()
+    assert h.T_s == p.T
+    assert h.counters["spill_overflow"] > 0 and h.counters["status"] == 3
+    # the totals are still whole: the box's one state (the start) plus the outside
+    assert h.outside + h.hist.sum() == pytest.approx(p.T, rel=1e-12)
+    ok = W.c4_toggle(seed=1, R=64, T=300.0, t_cp=1.0)
+    g2 = B.parrep_solve(ok, cycle_log_cap=0)
+    torch.cuda.synchronize()
+    h2 = g2.to_host()
+    assert h2.counters["spill_overflow"] == 0 and h2.counters["status"] == 0
+    srv = B.Server(n_streams=1)
+    t = srv.submit(p, min_runs=1, max_runs=1)
+    assert _code(B, lambda: srv.poll(t)) == -7
+    t = srv.submit(ok, min_runs=1, max_runs=1)
+    _, info = srv.poll(t)
+    assert info["status"] == 0
+    srv.close()
