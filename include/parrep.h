@@ -234,6 +234,28 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
                        const parrep_problem* probs, const parrep_result* res,
                        const parrep_launch* launch, void* stream);
 
+/* Bytes of the fixed device array that holds parrep_solve_noalloc's scratch. */
+#define PARREP_NOALLOC_SCRATCH_BYTES (2u << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as parrep_solve (equal outputs: integers exactly, floats up to
+ * summation order), but it calls no hipMalloc, hipFree or other allocating
+ * routine: the instance's descriptor and scratch (propensity table,
+ * outside-box accumulators, spill table, exchange and scan buffers) go to a
+ * fixed array of PARREP_NOALLOC_SCRATCH_BYTES in device memory that each GPU
+ * the library runs on holds until the process ends.  The descriptor is
+ * written by a kernel (no host copy), and the scratch is cleared by the
+ * solve's own kernels.  EINVAL when the problem's scratch exceeds the array
+ * (it grows with R and with the histogram box's largest coordinate: about
+ * 48 bytes per replica plus 64 bytes per table state; R = 65536 does not
+ * fit).  Every call on one GPU uses that GPU's one array, which keeps the
+ * last call's contents: calls whose work can overlap on the device (other
+ * streams, other threads, other contexts on the same GPU) race and give
+ * wrong results; order them on one stream. */
+int parrep_solve_noalloc(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
+                         const parrep_result* res, void* stream);
+
 /* ---- Batched form: plans ------------------------------------------------
  * A plan is a batch of instances prepared once: descriptors and scratch in
  * device memory the plan owns, the instances grouped by launch shape (the

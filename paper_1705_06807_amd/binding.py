@@ -102,6 +102,7 @@ def lib():
             L.parrep_problem_nbins.argtypes = [vp, C.POINTER(Problem)]
             L.parrep_problem_nbins.restype = C.c_int64
             L.parrep_solve.argtypes = [vp, vp, C.POINTER(Problem), C.POINTER(Result), vp]
+            L.parrep_solve_noalloc.argtypes = [vp, vp, C.POINTER(Problem), C.POINTER(Result), vp]
             L.parrep_solve_batch.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Problem),
                                              C.POINTER(Result), C.POINTER(Launch), vp]
             L.parrep_philox.argtypes = [vp, C.c_int64, vp, vp, vp]
@@ -304,6 +305,18 @@ def parrep_solve(p: W.Problem, ctx: Optional[Context] = None, stream=None,
     _check(lib().parrep_solve(ctx.h, ctx.net(p.net), C.byref(ps), C.byref(rs),
                               _stream_ptr(stream)))
     return out
+
+
+def parrep_solve_noalloc(p: W.Problem, outputs: "Outputs", ctx: Optional[Context] = None,
+                         stream=None) -> "Outputs":
+    """parrep_solve with its scratch in the library's fixed device array:
+    no device allocation in the call (outputs are allocated by the caller)."""
+    ctx = ctx or context()
+    ps = problem_struct(p)
+    rs = outputs.struct()
+    _check(lib().parrep_solve_noalloc(ctx.h, ctx.net(p.net), C.byref(ps), C.byref(rs),
+                                      _stream_ptr(stream)))
+    return outputs
 
 
 def parrep_solve_batch(problems: Sequence[W.Problem], ctx: Optional[Context] = None,

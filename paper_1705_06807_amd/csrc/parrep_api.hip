@@ -18,6 +18,12 @@
 
 using namespace parrep;
 
+// Scratch of parrep_solve_noalloc: one fixed array per device, held until the
+// process ends.  Host code never uses this name as an address (on the host
+// it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, once per device, in noalloc_scratch().
+static __device__ __align__(256) char scratch[PARREP_NOALLOC_SCRATCH_BYTES];
+
 namespace parrep {
 namespace host {
 
@@ -231,6 +237,23 @@ void place_arena(std::vector<DevInst>& insts, char* b, bool share) {
     }
 }
 
+// Device address of `scratch` on `device`, which must be current; looked up
+// once per device.
+int noalloc_scratch(int device, char** out) {
+    static std::mutex mu;
+    static std::map<int, char*> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        it = addr.emplace(device, static_cast<char*>(p)).first;
+    }
+    *out = it->second;
+    return PARREP_OK;
+}
+
 int set_device(parrep_ctx* ctx) {
     hipError_t e = hipSetDevice(ctx->device);
     return e == hipSuccess ? PARREP_OK : hip_fail(e, "hipSetDevice");
@@ -429,11 +452,13 @@ int parrep_ctx_create(int device, parrep_ctx** out) {
                                                    device);
     if (e == hipSuccess) e = hipMalloc(&c->logtab, sizeof(host_tab));
     if (e == hipSuccess) e = hipMemcpy(c->logtab, host_tab, sizeof(host_tab), hipMemcpyHostToDevice);
-    if (e != hipSuccess && c->logtab) (void)hipFree(c->logtab);
+    int rc = e == hipSuccess ? noalloc_scratch(device, &c->noalloc_scratch)
+                             : hip_fail(e, "context table upload");
+    if (rc != PARREP_OK && c->logtab) (void)hipFree(c->logtab);
     (void)hipSetDevice(prev);
-    if (e != hipSuccess) {
+    if (rc != PARREP_OK) {
         delete c;
-        return hip_fail(e, "context table upload");
+        return rc;
     }
     *out = c;
     return PARREP_OK;
@@ -566,6 +591,37 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
     std::lock_guard<std::mutex> lk(ctx->mu);
     return run_batch(ctx, insts, kModeSolve, 0, -1, (hipStream_t)stream, ev_b, ev_a,
                      force ? &forced : nullptr);
+}
+
+int parrep_solve_noalloc(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
+                         const parrep_result* res, void* stream) {
+    if (!ctx || !net || !prob || !res) return fail(PARREP_EINVAL, "NULL argument");
+    if (net->ctx != ctx) return fail(PARREP_EINVAL, "net was created in another context");
+    int64_t nb = 0;
+    int rc = validate_problem(net, prob, &nb);
+    if (rc) return rc;
+    rc = check_result(res);
+    if (rc) return rc;
+    std::vector<DevInst> insts(1);
+    fill_inst(insts[0], net, prob, nb);
+    attach_result(insts[0], res);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    rc = set_device(ctx);
+    if (rc) return rc;
+    if (!ctx->noalloc_scratch) return fail(PARREP_EDEVICE, "no scratch array on this device");
+    const std::vector<Group> groups = group_batch(ctx, insts, nullptr, nullptr);
+    const size_t bytes = arena_bytes(insts);
+    if (bytes > PARREP_NOALLOC_SCRATCH_BYTES)
+        return fail(PARREP_EINVAL, "the problem needs " + std::to_string(bytes) +
+                                       " bytes of scratch; the fixed array holds " +
+                                       std::to_string(PARREP_NOALLOC_SCRATCH_BYTES));
+    char* base = ctx->noalloc_scratch;
+    place_arena(insts, base);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_install(insts[0], reinterpret_cast<DevInst*>(base), st);
+    if (e != hipSuccess) return hip_fail(e, "descriptor install");
+    return enqueue_batch(ctx, reinterpret_cast<DevInst*>(base), 1, groups, kModeSolve, 0, -1, st,
+                         nullptr, nullptr);
 }
 
 int parrep_philox(parrep_ctx* ctx, int64_t n, const uint32_t* ctr_key, uint32_t* out,

@@ -24,6 +24,8 @@ struct parrep_ctx {
     // Autotuned launch shapes: (replica-count bucket, species, reaction class)
     // -> (replicas per lane, waves).
     std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+    // Device address of this device's fixed scratch array (parrep_solve_noalloc).
+    char* noalloc_scratch = nullptr;
 };
 
 struct parrep_net {

@@ -144,6 +144,8 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, in
 int table_lds_need(const DevInst& d, LaunchShape shape);
 int table_lds_doubles(LaunchShape shape, int max_need);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
+// Writes descriptor d (a kernel argument) to dst in device memory.
+hipError_t launch_install(const DevInst& d, DevInst* dst, hipStream_t stream);
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_finalize(const DevInst* d_inst, int n_inst, hipStream_t stream);
 hipError_t launch_accumulate(double* dst, const double* src, int64_t n, hipStream_t stream);

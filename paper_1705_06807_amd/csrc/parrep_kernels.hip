@@ -37,6 +37,19 @@ __global__ void __launch_bounds__(256) k_setup(DevInst* __restrict__ insts) {
 }
 
 // ---------------------------------------------------------------------------
+// Install one descriptor, passed by value, at dst (the allocation-free solve
+// writes its descriptor into fixed device memory without a host copy).
+// ---------------------------------------------------------------------------
+static_assert(sizeof(DevInst) % 8 == 0 && sizeof(DevInst) <= 3072,
+              "a descriptor must fit a kernel argument");
+
+__global__ void __launch_bounds__(64) k_install(DevInst d, DevInst* __restrict__ dst) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(&d);
+    uint64_t* out = reinterpret_cast<uint64_t*>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(DevInst) / 8); i += 64) out[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
 // Zero the accumulators of every instance.
 // ---------------------------------------------------------------------------
 __global__ void k_zero(const DevInst* __restrict__ insts) {
@@ -419,6 +432,11 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mo
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
 #undef PARREP_GO
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_install(const DevInst& d, DevInst* dst, hipStream_t stream) {
+    hipLaunchKernelGGL(k_install, dim3(1), dim3(64), 0, stream, d, dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream) {
