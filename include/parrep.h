@@ -96,6 +96,8 @@ enum {
 enum {
     PARREP_RUN_OK = 0,             /* the clock reached the horizon                   */
     PARREP_RUN_BUDGET = 1,         /* the event budget stopped the run first           */
+    PARREP_RUN_ABORTED = 2,        /* an instance spread over several workgroups gave up
+                                      waiting at a grid barrier (outputs incomplete)  */
     PARREP_RUN_SPILL_OVERFLOW = 3  /* the horizon was reached, but time at states
                                       outside the histogram box found no spill slot:
                                       FIM, RER and Y miss it (PARREP_CNT_SPILL_OVERFLOW
@@ -180,12 +182,30 @@ typedef struct {
 /* Launch shape for the batched solve: replicas per lane and waves per
  * workgroup (0 = let the library choose from the replica count), and two
  * optional hipEvent_t handles (NULL = none) recorded on the stream right
- * before and right after the instance kernel, so a caller can time it. */
+ * before and right after the instance kernel, so a caller can time it.
+ *
+ * A single-instance batch can instead spread its one instance over the
+ * workgroups of a cooperative launch (4 waves each, replicas_per_lane 1 or
+ * 4): the replicas are split into contiguous ranges that run their rounds
+ * independently and meet only at the end of chunks of rounds, where they
+ * agree on the first exit, the dephasing stop and the horizon, and replay
+ * the chunk up to that point (outputs equal the one-workgroup solve's:
+ * integers exactly, floats up to summation order).  workgroups: 0 = the
+ * library's choice (spread when R >= 8192 and no shape is forced, over
+ * ceil(R / (256 replicas_per_lane)) workgroups), 1 = one workgroup, n > 1 =
+ * spread over n (at least ceil(R / (256 replicas_per_lane)); no more than
+ * can be resident at once, else EDEVICE).  Each wait at a chunk's meeting
+ * point is bounded by barrier_wait_us (0 = 2 s); a run that gives up ends
+ * with status PARREP_RUN_ABORTED. */
 typedef struct {
     int32_t replicas_per_lane;  /* 1, 4 or 16; or 64 with 16 waves (R > 16384)       */
     int32_t waves;              /* 1, 4 or 16 (64-lane wavefronts per workgroup)      */
     void* event_before;         /* hipEvent_t or NULL                                 */
     void* event_after;          /* hipEvent_t or NULL                                 */
+    int32_t workgroups;         /* single-instance batches, see above                 */
+    int32_t chunk_rounds[2];    /* spread runs: dephasing and parallel-step chunk
+                                   lengths in rounds (0 = 512 and 64; the second <= 64) */
+    int32_t barrier_wait_us;    /* spread runs: longest wait at a meeting point       */
 } parrep_launch;
 
 /* Create a context on a HIP device: it owns the scratch arena and the

@@ -65,7 +65,9 @@ class Result(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("replicas_per_lane", C.c_int32), ("waves", C.c_int32),
-                ("event_before", C.c_void_p), ("event_after", C.c_void_p)]
+                ("event_before", C.c_void_p), ("event_after", C.c_void_p),
+                ("workgroups", C.c_int32), ("chunk_rounds", C.c_int32 * 2),
+                ("barrier_wait_us", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -322,15 +324,19 @@ def parrep_solve_noalloc(p: W.Problem, outputs: "Outputs", ctx: Optional[Context
 def parrep_solve_batch(problems: Sequence[W.Problem], ctx: Optional[Context] = None,
                        stream=None, replicas_per_lane: int = 0, waves: int = 0,
                        cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None,
-                       events=None) -> List[Outputs]:
-    """Many independent solves in one launch; returns per-instance device outputs."""
+                       events=None, workgroups: int = 0, chunk_rounds=(0, 0),
+                       barrier_wait_us: int = 0) -> List[Outputs]:
+    """Many independent solves in one launch; returns per-instance device outputs.
+    workgroups, chunk_rounds, barrier_wait_us: see parrep_launch (spreading a
+    single instance over workgroups)."""
     ctx = ctx or context()
     n = len(problems)
     outs = outputs if outputs is not None else [Outputs(ctx, p, cycle_log_cap) for p in problems]
     nets = (C.c_void_p * n)(*[ctx.net(p.net).value for p in problems])
     ps = (Problem * n)(*[problem_struct(p) for p in problems])
     rs = (Result * n)(*[o.struct() for o in outs])
-    la = Launch(replicas_per_lane, waves, None, None)
+    la = Launch(replicas_per_lane, waves, None, None, workgroups,
+                (C.c_int32 * 2)(*chunk_rounds), barrier_wait_us)
     if events is not None:  # (before, after) torch.cuda.Event pair, already created
         la.event_before, la.event_after = events[0].cuda_event, events[1].cuda_event
     _check(lib().parrep_solve_batch(ctx.h, n, nets, ps, rs, C.byref(la), _stream_ptr(stream)))

@@ -6,6 +6,7 @@ bit-level conventions the integer state sequence depends on);
 packed-FP32 target feature is switched off.
 """
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -36,16 +37,38 @@ def hipcc() -> str:
     return h
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
+def _includes(path, seen=None):
+    """The quoted #include files of path, recursively (the object's header deps)."""
+    seen = set() if seen is None else seen
+    with open(path) as f:
+        for line in f:
+            m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+            if m:
+                dep = os.path.normpath(os.path.join(os.path.dirname(path), m.group(1)))
+                if dep not in seen and os.path.exists(dep):
+                    seen.add(dep)
+                    _includes(dep, seen)
+    return seen
+
+
+def build(force: bool = True, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit and link libparrep.so.  force=False
+    returns at once when the library is newer than every source;
+    incremental=True recompiles only the objects older than their source or
+    one of the headers it includes."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     jobs = [(s, os.path.basename(s) + ".o", []) for s in srcs]
     inst = os.path.join(CSRC, "parrep_instance.hip")
     for ns, w in INSTANCE_VARIANTS:
         jobs.append((inst, "parrep_instance_ns%d_w%d.o" % (ns, w),
                      ["-DPARREP_NS=%d" % ns, "-DPARREP_WAVES=%d" % w]))
+    wide = os.path.join(CSRC, "parrep_wide.hip")
+    for ns in (1, 2, 4):
+        jobs.append((wide, "parrep_wide_ns%d.o" % ns, ["-DPARREP_NS=%d" % ns]))
     deps = srcs + [inst, os.path.join(CSRC, "parrep_internal.h"), os.path.join(CSRC, "parrep_host.h"),
                    os.path.join(CSRC, "parrep_neglog.h"), os.path.join(CSRC, "parrep_fx.h"),
-                   os.path.join(CSRC, "parrep_device.h"), os.path.join(ROOT, "include", "parrep.h")]
+                   os.path.join(CSRC, "parrep_device.h"), os.path.join(CSRC, "parrep_wide.h"),
+                   wide, os.path.join(ROOT, "include", "parrep.h")]
     if not force and os.path.exists(LIB):
         if os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):
             return LIB
@@ -55,6 +78,10 @@ def build(force: bool = True, verbose: bool = False) -> str:
     def compile_one(job):
         src, oname, defs = job
         obj = os.path.join(BUILD, oname)
+        if incremental and os.path.exists(obj):
+            newest = max(os.path.getmtime(d) for d in [src, *_includes(src)])
+            if os.path.getmtime(obj) >= newest:
+                return obj
         cmd = [cc, *FLAGS, *defs, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -76,4 +103,4 @@ def build(force: bool = True, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(force=True, verbose="-v" in sys.argv))
+    print(build(force=True, verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -176,7 +176,7 @@ std::string table_key(const DevInst& d) {
 // Offsets of each instance's scratch inside the arena.
 struct Layout {
     size_t total = 0;
-    std::vector<size_t> tab, acc, spill, xbuf, sbuf;
+    std::vector<size_t> tab, acc, spill, xbuf, sbuf, wide;
     std::vector<int> owner;
 };
 
@@ -188,6 +188,7 @@ Layout layout(const std::vector<DevInst>& insts, bool share) {
     L.spill.resize(n);
     L.xbuf.resize(n);
     L.sbuf.resize(n);
+    L.wide.resize(n);
     L.owner.resize(n);
     size_t off = align256(n * sizeof(DevInst));
     std::map<std::string, size_t> tables;
@@ -212,6 +213,12 @@ Layout layout(const std::vector<DevInst>& insts, bool share) {
         off = align256(off + (size_t)insts[i].R * kMaxS * sizeof(int32_t));
         L.sbuf[i] = off;
         off = align256(off + (size_t)insts[i].R * 4 * sizeof(uint64_t));
+        L.wide[i] = 0;
+        if (insts[i].wide_waves > 0) {  // exchange area, per-wave sums, survivor words
+            L.wide[i] = off;
+            off = align256(off + sizeof(WideSync) + (size_t)insts[i].wide_waves * 16 +
+                           (size_t)insts[i].wide_waves * insts[i].wide_rpl * 8);
+        }
     }
     L.total = off;
     return L;
@@ -234,6 +241,16 @@ void place_arena(std::vector<DevInst>& insts, char* b, bool share) {
         insts[i].spill = reinterpret_cast<SpillSlot*>(b + L.spill[i]);
         insts[i].xbuf = reinterpret_cast<int32_t*>(b + L.xbuf[i]);
         insts[i].sbuf = reinterpret_cast<uint64_t*>(b + L.sbuf[i]);
+        if (insts[i].wide_waves > 0) {
+            char* w = b + L.wide[i];
+            insts[i].wide = reinterpret_cast<WideSync*>(w);
+            insts[i].wtot = reinterpret_cast<uint64_t*>(w + sizeof(WideSync));
+            insts[i].smask = reinterpret_cast<uint64_t*>(w + sizeof(WideSync) +
+                                                         (size_t)insts[i].wide_waves * 16);
+        } else {
+            insts[i].wide = nullptr;
+            insts[i].wtot = insts[i].smask = nullptr;
+        }
     }
 }
 
@@ -333,8 +350,11 @@ int enqueue_batch(parrep_ctx* ctx, DevInst* d, int n, const std::vector<Group>& 
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     if (groups.size() == 1) {
         const Group& g = groups[0];
-        e = launch_solve(d + g.first, g.count, g.shape, mode, hook_cycle, hook_max_rounds,
-                         g.tab_lds, st);
+        if (g.shape.wide)
+            e = launch_wide(d + g.first, g.shape, g.tab_lds, st);
+        else
+            e = launch_solve(d + g.first, g.count, g.shape, mode, hook_cycle, hook_max_rounds,
+                             g.tab_lds, st);
     } else {
         // Fork: group 0 on st, the others on auxiliary streams; join into st.
         while (ctx->aux.size() + 1 < groups.size()) {
@@ -374,12 +394,49 @@ int enqueue_batch(parrep_ctx* ctx, DevInst* d, int n, const std::vector<Group>& 
     return e == hipSuccess ? PARREP_OK : hip_fail(e, "kernel launch");
 }
 
+int apply_wide(parrep_ctx* ctx, std::vector<DevInst>& insts, std::vector<Group>& groups,
+               const WideReq& w) {
+    if (insts.size() != 1 || groups.size() != 1 || w.workgroups == 1) return PARREP_OK;
+    DevInst& d = insts[0];
+    const int rpl = w.rpl > 0 ? w.rpl : 1;
+    if (rpl != 1 && rpl != 4) return fail(PARREP_EINVAL, "spread instances take 1 or 4 replicas per lane");
+    const int need = (d.R + 256 * rpl - 1) / (256 * rpl);
+    int G = 0;
+    if (w.workgroups > 1) {
+        if (w.workgroups < need)
+            return fail(PARREP_EINVAL, "workgroups x 256 lanes x replicas per lane < R");
+        G = w.workgroups;
+    } else if (d.R >= kWideMinR) {
+        G = need;
+    }
+    if (G < 2) return PARREP_OK;
+    if ((int64_t)G * 256 * rpl > PARREP_MAX_REPLICAS + 256 * rpl - 1)
+        return fail(PARREP_EINVAL, "more workgroups than the replica capacity needs");
+    if (w.s3 > kWideS3Max) return fail(PARREP_EINVAL, "parallel-step chunk longer than 64 rounds");
+    Group& g = groups[0];
+    g.shape.rpl = rpl;
+    g.shape.waves = 4;
+    g.shape.wide = G;
+    g.tab_lds = table_lds_doubles(g.shape, table_lds_need(d, g.shape));
+    d.wide_waves = 4 * G;
+    d.wide_rpl = rpl;
+    d.wide_s2 = w.s2 > 0 ? w.s2 : kWideChunkS2;
+    d.wide_s3 = w.s3 > 0 ? w.s3 : kWideChunkS3;
+    const double wait_s = (w.wait_us > 0 ? w.wait_us : 2000000) * 1e-6;
+    d.wide_wait_ticks = std::max<int64_t>(1, (int64_t)(wait_s * ctx->wall_hz));
+    return PARREP_OK;
+}
+
 int run_batch(parrep_ctx* ctx, std::vector<DevInst>& insts, int mode, uint32_t hook_cycle,
               int64_t hook_max_rounds, hipStream_t st, hipEvent_t ev_b, hipEvent_t ev_a,
-              const LaunchShape* forced) {
+              const LaunchShape* forced, const WideReq* wide) {
     int rc = set_device(ctx);
     if (rc) return rc;
     std::vector<Group> groups = group_batch(ctx, insts, nullptr, forced);
+    if (mode == kModeSolve) {
+        rc = apply_wide(ctx, insts, groups, wide ? *wide : WideReq{});
+        if (rc) return rc;
+    }
     const size_t bytes = arena_bytes(insts);
     void* base = nullptr;
     hipError_t e = hipMallocAsync(&base, bytes, st);
@@ -450,6 +507,11 @@ int parrep_ctx_create(int device, parrep_ctx** out) {
     if (e == hipSuccess) e = hipSetDevice(device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
                                                    device);
+    int wall_khz = 0;
+    if (e == hipSuccess &&
+        hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess &&
+        wall_khz > 0)
+        c->wall_hz = 1e3 * wall_khz;
     if (e == hipSuccess) e = hipMalloc(&c->logtab, sizeof(host_tab));
     if (e == hipSuccess) e = hipMemcpy(c->logtab, host_tab, sizeof(host_tab), hipMemcpyHostToDevice);
     int rc = e == hipSuccess ? noalloc_scratch(device, &c->noalloc_scratch)
@@ -579,7 +641,8 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
     hipEvent_t ev_b = launch ? (hipEvent_t)launch->event_before : nullptr;
     hipEvent_t ev_a = launch ? (hipEvent_t)launch->event_after : nullptr;
     LaunchShape forced{};
-    const bool force = launch && (launch->replicas_per_lane > 0 || launch->waves > 0);
+    const bool spread = launch && launch->workgroups > 1;
+    const bool force = !spread && launch && (launch->replicas_per_lane > 0 || launch->waves > 0);
     if (force) {
         forced = choose_shape(maxR, maxS, kMaxM);
         forced.rpl = launch->replicas_per_lane > 0 ? launch->replicas_per_lane : forced.rpl;
@@ -588,9 +651,27 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
             return fail(PARREP_EINVAL, "launch shape holds fewer replicas than R");
         if (!shape_supported(forced)) return fail(PARREP_EUNSUPPORTED, "launch shape not compiled in");
     }
+    WideReq wide;
+    if (launch) {
+        if (launch->workgroups < 0 || launch->chunk_rounds[0] < 0 || launch->chunk_rounds[1] < 0 ||
+            launch->barrier_wait_us < 0)
+            return fail(PARREP_EINVAL, "negative workgroups, chunk length or wait");
+        wide.workgroups = launch->workgroups;
+        // a forced one-workgroup shape stays one workgroup unless spreading is asked for
+        if (force && launch->workgroups == 0) wide.workgroups = 1;
+        if (launch->workgroups > 1) {
+            if (count != 1) return fail(PARREP_EINVAL, "only a single-instance batch is spread over workgroups");
+            wide.rpl = launch->replicas_per_lane;
+            if (launch->waves != 0 && launch->waves != 4)
+                return fail(PARREP_EINVAL, "spread instances run 4 waves per workgroup");
+        }
+        wide.s2 = launch->chunk_rounds[0];
+        wide.s3 = launch->chunk_rounds[1];
+        wide.wait_us = launch->barrier_wait_us;
+    }
     std::lock_guard<std::mutex> lk(ctx->mu);
     return run_batch(ctx, insts, kModeSolve, 0, -1, (hipStream_t)stream, ev_b, ev_a,
-                     force ? &forced : nullptr);
+                     force ? &forced : nullptr, &wide);
 }
 
 int parrep_solve_noalloc(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,

@@ -895,7 +895,7 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
                                             const double* __restrict__ ltab,
                                             const double* __restrict__ lgt, RunState& rs, Fx Tq,
                                             Fx tbq, int64_t max_ev, uint32_t key0, uint32_t key1,
-                                            int lane) {
+                                            int lane, bool accum = true) {
     const bool steps = I->decorr_mode == PARREP_STEPS;
     const int64_t n_c = (int64_t)I->decorr;
     const double t_c = I->decorr;
@@ -995,7 +995,7 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
         }
         if (lane < n_eff) {
             Fx cn;
-            credit_event<NS>(I, xpre_l, tau_l, cpre_l, Tq, tbq, true, cn);
+            credit_event<NS>(I, xpre_l, tau_l, cpre_l, Tq, tbq, accum, cn);
         }
         const int last = n_eff - 1;
         ev += n_eff;

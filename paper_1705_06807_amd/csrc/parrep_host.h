@@ -26,6 +26,8 @@ struct parrep_ctx {
     std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
     // Device address of this device's fixed scratch array (parrep_solve_noalloc).
     char* noalloc_scratch = nullptr;
+    double wall_hz = 1e8;  // rate of the device's constant wall clock
+    int max_wide_groups = 0;  // co-resident workgroups of the wide kernel (0: not yet known)
 };
 
 struct parrep_net {
@@ -88,10 +90,24 @@ int enqueue_batch(parrep_ctx* ctx, DevInst* d, int n, const std::vector<Group>& 
                   int mode, uint32_t hook_cycle, int64_t hook_max_rounds, hipStream_t st,
                   hipEvent_t ev_b, hipEvent_t ev_a, std::vector<hipEvent_t>* keep = nullptr);
 
+// How a single-instance solve may be spread over the workgroups of a
+// cooperative launch (parrep_launch's fields).
+struct WideReq {
+    int workgroups = 0;  // 0 library choice (spread when R >= kWideMinR), 1 never, > 1 that many
+    int rpl = 0;         // replicas per lane, 1 or 4 (0: 1)
+    int s2 = 0, s3 = 0;  // chunk lengths in rounds (0: defaults)
+    int wait_us = 0;     // longest wait at a grid barrier (0: 2 s)
+};
+// Rewrites the only group of a one-instance solve to the wide kernel when w
+// asks for it or R is large, and sets the instance's wide fields (before
+// the arena is laid out).  EINVAL when the request cannot hold R.
+int apply_wide(parrep_ctx* ctx, std::vector<DevInst>& insts, std::vector<Group>& groups,
+               const WideReq& w);
+
 // Whole batch with a stream-ordered arena: allocate, upload, enqueue, free.
 int run_batch(parrep_ctx* ctx, std::vector<DevInst>& insts, int mode, uint32_t hook_cycle,
               int64_t hook_max_rounds, hipStream_t st, hipEvent_t ev_b, hipEvent_t ev_a,
-              const LaunchShape* forced);
+              const LaunchShape* forced, const WideReq* wide = nullptr);
 
 }  // namespace host
 }  // namespace parrep

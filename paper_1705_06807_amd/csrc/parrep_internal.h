@@ -46,6 +46,23 @@ struct SpillSlot {
 };
 constexpr int kSpillCap = 2048;
 
+// Exchange area of one instance spread over several workgroups (the wide
+// instance kernel): a grid barrier, the chunk results the workgroups agree
+// on (triple-buffered by chunk index), and broadcast states.  k_zero
+// initialises it before the kernel runs.
+constexpr int kWideS3Max = 64;  // longest parallel-step chunk (rounds)
+struct WideSync {
+    uint32_t bar;     // barrier arrivals (wraps; compared modulo 2^32)
+    uint32_t abort;   // a workgroup gave up waiting: every workgroup leaves
+    int64_t rend;     // replica whose holding interval holds the horizon
+    int64_t e2[3];    // dephasing chunk: first round with an exit (min)
+    int64_t d2[3];    // dephasing chunk: round after which every replica is done (max)
+    uint64_t k3[3];   // parallel chunk: first exit key R n + r (min)
+    int32_t xb[kMaxS], xf[kMaxS];  // broadcast: exit state; state at the horizon
+    uint64_t s3[3][kWideS3Max][3];  // parallel chunk: per-round clock sums, 64.64
+                                    // split as (hi, lo >> 32, lo & 0xffffffff)
+};
+
 struct DevInst {
     DevNet net;
     double c[kMaxP], rer_eps[kMaxP];
@@ -83,6 +100,13 @@ struct DevInst {
     SpillSlot* spill;    // kSpillCap slots: time at states outside the histogram box
     int32_t* xbuf;       // 2 * R * kMaxS: Fleming-Viot state exchange (two rounds)
     uint64_t* sbuf;      // R * 4: boundary-round clock scan (tau, start) as 64.64
+    // wide instance kernel only (NULL otherwise)
+    WideSync* wide;
+    uint64_t* wtot;      // per wave: its replicas' clock sum in the exact round (64.64)
+    uint64_t* smask;     // per 64 replicas: survivors of a Fleming-Viot round
+    int32_t wide_s2, wide_s3;   // chunk lengths (rounds) of dephasing and parallel step
+    int64_t wide_wait_ticks;    // wall-clock ticks a workgroup waits at a grid barrier
+    int32_t wide_waves, wide_rpl;  // waves of the launch and replicas per lane (0: not wide)
     // test-hook outputs (unused by full solves)
     int32_t* hook_states;   // dephase-only: output states; parallel-only: input states
     int32_t* hook_exit;     // parallel-only: exit state
@@ -130,7 +154,8 @@ __host__ __device__ constexpr bool narrow_kernel(int ns, int m) { return ns <= 2
 
 struct LaunchShape {
     int rpl, waves, ns;
-    int m;  // reactions (the kernel is specialised for m <= 4 and m <= 8)
+    int m;         // reactions (the kernel is specialised for m <= 4 and m <= 8)
+    int wide = 0;  // > 0: one instance over this many workgroups (4 waves each)
 };
 
 // Launchers (parrep_kernels.hip).
@@ -144,6 +169,12 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, in
 int table_lds_need(const DevInst& d, LaunchShape shape);
 int table_lds_doubles(LaunchShape shape, int max_need);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
+// One instance over s.wide workgroups (cooperative launch; s.rpl 1 or 4).
+hipError_t launch_wide(const DevInst* d_inst, LaunchShape s, int tab_lds, hipStream_t stream);
+// Replica count from which a single-instance solve is spread over
+// workgroups by default, and the default chunk lengths (rounds).
+constexpr int kWideMinR = 8192;
+constexpr int kWideChunkS2 = 512, kWideChunkS3 = 64;
 // Writes descriptor d (a kernel argument) to dst in device memory.
 hipError_t launch_install(const DevInst& d, DevInst* dst, hipStream_t stream);
 hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream);

@@ -71,6 +71,20 @@ __global__ void k_zero(const DevInst* __restrict__ insts) {
     if (I->cycle_log)
         for (int64_t i = t0; i < (int64_t)I->cycle_log_cap * PARREP_CYCLE_REC; i += stride)
             I->cycle_log[i] = 0;
+    if (I->wide) {
+        WideSync* ws = I->wide;
+        if (t0 == 0) {
+            ws->bar = 0;
+            ws->abort = 0;
+            ws->rend = -1;
+            for (int q = 0; q < 3; ++q) {
+                ws->e2[q] = INT64_MAX;
+                ws->d2[q] = -1;
+                ws->k3[q] = ~0ull;
+            }
+        }
+        for (int64_t i = t0; i < 3 * kWideS3Max * 3; i += stride) (&ws->s3[0][0][0])[i] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -434,6 +448,18 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mo
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_wide_ns1(const DevInst*, int, int, int, int, hipStream_t);
+hipError_t launch_wide_ns2(const DevInst*, int, int, int, int, hipStream_t);
+hipError_t launch_wide_ns4(const DevInst*, int, int, int, int, hipStream_t);
+
+hipError_t launch_wide(const DevInst* d_inst, LaunchShape s, int tab_lds, hipStream_t stream) {
+    if (s.wide < 1 || s.waves != 4 || (s.rpl != 1 && s.rpl != 4)) return hipErrorInvalidValue;
+    if (s.ns == 1) return launch_wide_ns1(d_inst, s.wide, s.m, s.rpl, tab_lds, stream);
+    if (s.ns == 2) return launch_wide_ns2(d_inst, s.wide, s.m, s.rpl, tab_lds, stream);
+    if (s.ns == 4) return launch_wide_ns4(d_inst, s.wide, s.m, s.rpl, tab_lds, stream);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_install(const DevInst& d, DevInst* dst, hipStream_t stream) {
     hipLaunchKernelGGL(k_install, dim3(1), dim3(64), 0, stream, d, dst);
     return hipGetLastError();
@@ -454,7 +480,8 @@ int table_lds_need(const DevInst& d, LaunchShape s) {
 }
 
 int table_lds_doubles(LaunchShape s, int max_need) {
-    const size_t xb = xbuf_lds_bytes(s.rpl, s.waves, s.ns);
+    // the wide kernel runs one workgroup per CU and exchanges through HBM
+    const size_t xb = s.wide ? 0 : xbuf_lds_bytes(s.rpl, s.waves, s.ns);
     // leaves room for the static LDS of the kernel (24 KB more of it with 64
     // replicas per lane: the survivor masks and counts of 1024 slots)
     const size_t budget = (s.rpl == 64 ? 32 : 56) * 1024;
