@@ -188,16 +188,47 @@ def cpu_baseline(seconds: float, T_sample: float):
                       "time" % (n, T_sample, threads, wall)}
 
 
-def forms(B, W, ctx, args):
-    """Batched and served forms on mixed workloads with short horizons (so
-    that the plain one-at-a-time baseline stays affordable): solves/s of a
-    hipGraph plan vs sequential plain solves, and a Poisson request stream
-    served with continuous batching (p50/p99 request latency)."""
+def _toggle_law(omega):
+    """Exact stationary law of the toggle switch at this Omega on its
+    histogram box [0, 8 Omega]^2: a truncated-generator solve on
+    [0, 6 Omega]^2 (the mass beyond is below 1e-16; at Omega = 50 it agrees
+    with the solve on the whole box to 1.5e-13 in TV), zero outside."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import exact_laws as E
+    n, N = int(round(6 * omega)), int(round(8 * omega))
+    _, pi = E.toggle_pi(float(omega), n)
+    out = np.zeros((N + 1, N + 1))
+    out[:n + 1, :n + 1] = pi.reshape(n + 1, n + 1)
+    return out
+
+
+def start_toggle_laws(problems, workers):
+    """Start the exact laws of the toggle instances with Omega <= 50 in a
+    process pool (host CPU work that overlaps the GPU measurements)."""
+    from concurrent.futures import ProcessPoolExecutor
+    oms = sorted({p.hist_hi[0] / 8.0 for p in problems
+                  if p.net.name == "toggle" and p.hist_hi[0] <= 400})
+    ex = ProcessPoolExecutor(max_workers=max(1, min(workers, len(oms))))
+    return ex, {om: ex.submit(_toggle_law, om) for om in oms}
+
+
+def forms(B, W, ctx, args, laws=None):
+    """Batched and served forms at the configured horizons (Schloegl T = 200,
+    toggle T = 2e4).  Batched: the 256-instance mix as one hipGraph plan
+    launch, against the same 256 instances solved one at a time.  Served: a
+    Poisson request stream with continuous batching (p50/p99 latency),
+    against the same requests' runs solved one at a time.  Accuracy: every
+    batched and served output equals its plain solve (integers exactly,
+    floats to 1e-12), and the pooled stationary histogram of the toggle
+    instances with Omega <= 50 is compared with the mixture of their exact
+    laws in total variation."""
     import numpy as np
     import torch
 
-    Tf = args.forms_T
-    probs = W.c3_batch(seed=0, n_schlogl=128, n_toggle=128, T_schlogl=Tf, T_toggle=Tf)
+    Tt = args.forms_T
+    probs = W.c3_batch(seed=0, n_schlogl=128, n_toggle=128, T_toggle=Tt)
+    law_pool, law_futures = laws if laws is not None else start_toggle_laws(probs, 4)
     plan = B.Plan(probs, ctx=ctx)
     plan.launch()
     torch.cuda.synchronize()
@@ -206,23 +237,55 @@ def forms(B, W, ctx, args):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     batched = len(probs) / t_batch
+    bh = [o.to_host() for o in plan.outputs]
     plan.close()
-    def plain_rate(ps):
+    log("forms: batched %d instances in %.2f s" % (len(probs), t_batch))
+
+    def plain_solves(ps):
+        outs = []
         t0 = time.perf_counter()
         for p in ps:
-            B.parrep_solve(p, ctx=ctx, cycle_log_cap=0)
+            o = B.parrep_solve(p, ctx=ctx, cycle_log_cap=0)
             torch.cuda.synchronize()
-        return len(ps) / (time.perf_counter() - t0)
+            outs.append(o)
+        return time.perf_counter() - t0, [o.to_host() for o in outs]
 
-    sample = probs[::16]
-    plain = plain_rate(sample)
-    log("forms: batched %.1f solves/s, plain %.2f solves/s" % (batched, plain))
+    t_plain, ph = plain_solves(probs)
+    plain = len(probs) / t_plain
+    log("forms: plain %d instances one at a time in %.2f s" % (len(probs), t_plain))
+
+    def same(a, b):
+        if a.counters != b.counters or a.T_s != b.T_s:
+            return False
+        scale = max(np.abs(b.hist).max(), 1e-300)
+        return bool(np.abs(a.hist - b.hist).max() <= 1e-12 * scale)
+
+    batch_equal = all(same(a, b) for a, b in zip(bh, ph))
+    # pooled TV of the Omega <= 50 toggle instances against the mixture of exact laws
+    laws = {}
+    emp = None
+    mix = None
+    n_tv = 0
+    for p, h in zip(probs, bh):
+        if p.net.name != "toggle" or p.hist_hi[0] > 400:
+            continue
+        om = p.hist_hi[0] / 8.0
+        if om not in laws:
+            laws[om] = law_futures[om].result()
+        if emp is None:
+            emp = np.zeros((401, 401))
+            mix = np.zeros((401, 401))
+        n1 = p.hist_hi[0] + 1
+        emp[:n1, :n1] += h.hist
+        mix[:n1, :n1] += laws[om] * p.T
+        n_tv += 1
+    tv = 0.5 * float(np.abs(emp / emp.sum() - mix / mix.sum()).sum()) if n_tv else None
+    law_pool.shutdown()
 
     # served: Poisson arrivals at 0.8 x the batched capacity in requests/s
-    runs_min, runs_max = 4, 16
+    runs_min, runs_max = args.serve_runs
     rate = 0.8 * batched / (0.5 * (runs_min + runs_max))
-    arrivals, reqs = W.c5_requests(seed=0, n=args.serve_requests, rate=rate, T_schlogl=Tf,
-                                   T_toggle=Tf)
+    arrivals, reqs = W.c5_requests(seed=0, n=args.serve_requests, rate=rate, T_toggle=Tt)
     srv = B.Server(ctx=ctx, n_streams=4)
     t_start = time.perf_counter()
     tickets = []
@@ -231,28 +294,49 @@ def forms(B, W, ctx, args):
         if dt > 0:
             time.sleep(dt)
         tickets.append(srv.submit(p, rse_target=0.02, min_runs=runs_min, max_runs=runs_max))
-    infos = [srv.poll(t)[1] for t in tickets]
+    done = [srv.poll(t) for t in tickets]
     t_serve = time.perf_counter() - t_start
     srv.close()
-    plain_c5 = plain_rate(reqs[::6])
-    lat = np.array([i["latency_s"] for i in infos])
+    infos = [d[1] for d in done]
     runs = int(sum(i["runs"] for i in infos))
+    log("forms: served %d requests (%d runs) in %.2f s" % (len(reqs), runs, t_serve))
+    # the same runs, one plain solve each (instance ids prob.instance_id + k)
+    run_probs = [p.replace(instance_id=p.instance_id + k)
+                 for p, i in zip(reqs, infos) for k in range(i["runs"])]
+    t_plain5, ph5 = plain_solves(run_probs)
+    log("forms: plain %d runs one at a time in %.2f s" % (len(run_probs), t_plain5))
+    # each pooled request equals the sum of its runs solved alone
+    served_equal = True
+    k = 0
+    for (pooled, info), p in zip(done, reqs):
+        alone = ph5[k:k + info["runs"]]
+        k += info["runs"]
+        hsum = sum(a.hist for a in alone)
+        scale = max(np.abs(hsum).max(), 1e-300)
+        served_equal &= bool(np.abs(pooled.hist - hsum).max() <= 1e-12 * scale)
+        served_equal &= pooled.counters["ev_decorr"] == sum(a.counters["ev_decorr"] for a in alone)
+    lat = np.array([i["latency_s"] for i in infos])
     met = sum(1 for i in infos if i["rse"] <= 0.02)
     large = large_single_run(B, W, ctx) if not args.no_large else None
     return {
-        "workload": "C3 mix (128 Schloegl c x logU[0.9,1.1], 128 toggle Omega~U{25..100}, "
-                    "R~logU[64,4096]) and C5 stream (Schloegl / toggle Omega~U{25..150}, "
-                    "R~logU[256,16384]), both with horizon T=%g" % Tf,
+        "workload": "C3 mix (128 Schloegl c x logU[0.9,1.1] T=200, 128 toggle Omega~U{25..100} "
+                    "T=%g, R~logU[64,4096]) and C5 stream (Schloegl T=200 / toggle "
+                    "Omega~U{25..150} T=%g, R~logU[256,16384], %d-%d runs per request, "
+                    "2%% RSE target)" % (Tt, Tt, runs_min, runs_max),
         "batched_solves_per_s": batched,
         "plain_solves_per_s": plain,
         "batched_over_plain": batched / plain,
-        "plain_sample": "%d of the 256 instances solved one at a time" % len(sample),
+        "plain_sample": "all %d instances solved one at a time" % len(probs),
+        "batched_equals_plain": batch_equal,
+        "tv_pooled_toggle_omega_le_50": tv,
+        "tv_instances": n_tv,
         "served": {
             "requests": len(infos), "arrival_rate_per_s": rate,
-            "runs": runs, "solves_per_s": runs / t_serve,
-            "plain_solves_per_s": plain_c5,
-            "plain_sample": "%d of the requests' first runs solved one at a time" % len(reqs[::6]),
-            "served_over_plain": (runs / t_serve) / plain_c5,
+            "runs": runs, "seconds": t_serve, "solves_per_s": runs / t_serve,
+            "plain_solves_per_s": len(run_probs) / t_plain5,
+            "plain_sample": "the same %d runs solved one at a time" % len(run_probs),
+            "served_over_plain": (runs / t_serve) / (len(run_probs) / t_plain5),
+            "served_equals_plain": served_equal,
             "latency_p50_s": float(np.percentile(lat, 50)),
             "latency_p99_s": float(np.percentile(lat, 99)),
             "rse_target": 0.02, "runs_per_request": [runs_min, runs_max],
@@ -263,22 +347,35 @@ def forms(B, W, ctx, args):
 
 
 def large_single_run(B, W, ctx):
-    """One solve of the large single run (toggle Omega = 150, R = 65536,
-    T = 1e5, histogram [0, 1200]^2): wall time and events/s of one instance,
-    which occupies one workgroup of 16 waves with 64 replicas per lane."""
+    """The large single run (toggle Omega = 150, R = 65536, T = 1e5,
+    histogram [0, 1200]^2): one instance spread over 256 workgroups (the
+    library's choice for R >= 8192), timed after one untimed run, beside the
+    same instance on one workgroup of 16 waves; both must agree."""
+    import numpy as np
     import torch
     p = W.c4_toggle(seed=0)
     out = B.Outputs(ctx, p, cycle_log_cap=0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    B.parrep_solve_batch([p], ctx=ctx, outputs=[out])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    h = out.to_host()
+    res = {}
+    for name, kw in (("spread", {}), ("one_workgroup", {"workgroups": 1})):
+        for rep in range(2 if name == "spread" else 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.parrep_solve_batch([p], ctx=ctx, outputs=[out], **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        res[name] = (dt, out.to_host())
+    dt, h = res["spread"]
+    dt1, h1 = res["one_workgroup"]
     ev = h.events
-    log("large single run: %.2f s, %.3g events/s" % (dt, ev / dt))
-    return {"workload": "toggle Omega=150, R=65536, t_c=t_p=20, T=1e5, hist [0,1200]^2, one instance",
+    same = (h.counters == h1.counters and
+            bool(np.abs(h.hist - h1.hist).max() <= 1e-12 * np.abs(h1.hist).max()))
+    log("large single run: %.3f s spread, %.2f s on one workgroup" % (dt, dt1))
+    return {"workload": "toggle Omega=150, R=65536, t_c=t_p=20, T=1e5, hist [0,1200]^2, one "
+                        "instance",
+            "launch": "256 workgroups x 4 waves, 1 replica per lane, chunks 512/64 rounds",
             "seconds": dt, "events": int(ev), "events_per_s": ev / dt,
+            "one_workgroup_seconds": dt1, "one_workgroup_events_per_s": ev / dt1,
+            "spread_equals_one_workgroup": same,
             "cycles": int(h.counters["cycles"]), "reached_T": h.T_s == p.T}
 
 
@@ -300,8 +397,13 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched / served measurement")
-    ap.add_argument("--forms-T", type=float, default=200.0)
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--forms-T", type=float, default=2e4,
+                    help="toggle horizon of the batched and served forms (Schloegl: 200)")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-runs", type=int, nargs=2, default=(4, 8), metavar=("MIN", "MAX"),
+                    help="runs per served request")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="measure only the batched / served forms")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large single run (R = 65536) in the forms section")
     ap.add_argument("--phase-clock", action="store_true",
@@ -323,15 +425,24 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    from paper_1705_06807_amd import workloads as W
+    laws = None
+    if not args.no_forms:
+        # forked before this process touches the GPU
+        laws = start_toggle_laws(W.c3_batch(seed=0, n_schlogl=128, n_toggle=128,
+                                            T_toggle=args.forms_T), 4)
+
     import torch
     from paper_1705_06807_amd import binding as B
-    from paper_1705_06807_amd import workloads as W
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     B.lib()
     ctx = B.context(0)
+    if args.forms_only:
+        print(json.dumps({"forms": forms(B, W, ctx, args, laws)}), flush=True)
+        return
     toggle = args.workload == "toggle"
     if toggle:
         probs = [W.c2_toggle(seed=0, instance_id=i, T=args.T) for i in range(args.instances)]
@@ -442,7 +553,7 @@ def main():
             "parallel": pc[:, 2].mean().item(), "total_mean": tot.mean().item(),
             "total_max": tot.max().item(), "total_min": tot.min().item()}
     if not args.no_forms:
-        line["forms"] = forms(B, W, ctx, args)
+        line["forms"] = forms(B, W, ctx, args, laws)
     if not args.no_cpu_baseline:
         log("cpu baseline: %d threads, >= %.0f s" % (host_cpus()["usable"], args.cpu_seconds))
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.cpu_T)
