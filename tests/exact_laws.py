@@ -416,3 +416,30 @@ def decorr_events_pmf(a0: float, p_flip: float, t_c: float, k_max: int) -> np.nd
     for kk in range(1, k_max + 1):
         f[kk] = g[kk] + np.dot(h[1:kk], f[kk - 1:0:-1])
     return f
+
+
+def toggle_well_law(omega, u_lo, u_hi, v_lo, v_hi, c=(3.0, 3.0, 2.0, 2.0)):
+    """Stationary law of the toggle switch restricted to the box
+    [u_lo, u_hi] x [v_lo, v_hi] (transitions leaving the box dropped).  For a
+    box around one well, many standard deviations wide and far from the
+    other well, this is the law of the process conditioned on that well, as
+    long as the time horizon is far below the switching time.  Returns the
+    (u_hi - u_lo + 1, v_hi - v_lo + 1) array."""
+    gu = np.arange(u_lo, u_hi + 1)
+    gv = np.arange(v_lo, v_hi + 1)
+    U, V = np.meshgrid(gu, gv, indexing="ij")
+    U, V = U.ravel(), V.ravel()
+    nu, nv = len(gu), len(gv)
+    lam = toggle_rates(U, V, omega, c)
+    rows, cols, vals = [], [], []
+    for j, (du, dv) in enumerate(TOGGLE_STOICH):
+        u2, v2 = U + du, V + dv
+        ok = (u2 >= u_lo) & (u2 <= u_hi) & (v2 >= v_lo) & (v2 <= v_hi) & (lam[j] > 0)
+        rows.append((U[ok] - u_lo) * nv + (V[ok] - v_lo))
+        cols.append((u2[ok] - u_lo) * nv + (v2[ok] - v_lo))
+        vals.append(lam[j][ok])
+    n = nu * nv
+    Q = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n)).tocsr()
+    Q = Q - sp.diags(np.asarray(Q.sum(axis=1)).ravel())
+    return stationary_from_generator(Q.tocsr()).reshape(nu, nv)

@@ -123,6 +123,9 @@ C1_CASES = [
     ("c1_budget", lambda i: W.c1_schlogl(seed=5, instance_id=i).replace(max_events=20000 + 997 * i)),
     ("c1_narrow_hist", lambda i: W.c1_schlogl(seed=6, instance_id=i).replace(
         hist_lo=(60,), hist_hi=(110,))),
+    # the paper's own setting (Sec. IV A): V = 25, W+ = {x <= 25.96}, n_c = n_p = 5000
+    # transitions, R = 100, with the horizon cut from 1e5 to 5000 (about 10 exits)
+    ("paper_schlogl_v25", lambda i: W.paper_schlogl_problem(seed=5, instance_id=i, T=5000.0)),
     # degenerate thresholds: no decorrelation and no dephasing (every cycle is S3 from X~)
     ("c1_zero_thresholds", lambda i: W.c1_schlogl(seed=7, instance_id=i).replace(
         decorr_mode=W.STEPS, decorr=0, dephase_mode=W.STEPS, dephase=0)),
@@ -374,3 +377,32 @@ def test_full_size_c4_properties(B):
     assert c["ev_dephase"] == c["s2_rounds"] * p.R
     assert c["ev_par_credited"] + c["ev_par_discarded"] == c["s3_rounds"] * p.R
     assert np.all(h.fim.diagonal() > 0)
+
+
+STAGED_CASES = [
+    # one species: the whole box (1001 bins) fits the 1024-bin tile
+    ("c1", lambda i: W.c1_schlogl(seed=51, instance_id=i)),
+    ("paper_schlogl_v25", lambda i: W.paper_schlogl_problem(seed=52, instance_id=i, T=2000.0)),
+    # two species: a tile of the 41 x 41 box, with exits and restarts
+    ("om5_R1000", lambda i: _toggle_small(i, R=1000, T=60.0)),
+    # the benchmark's box (401 x 401) and shape, horizon cut
+    ("om50_R1024_t20", lambda i: W.c2_toggle(seed=53, instance_id=i, T=120.0)),
+]
+
+
+@pytest.mark.parametrize("flush", [0, 1, 7])
+@pytest.mark.parametrize("case", STAGED_CASES, ids=[c[0] for c in STAGED_CASES])
+def test_histogram_staging_parity(B, oracle, case, flush):
+    """Parallel-step credits staged in an LDS tile of the histogram and
+    flushed at the step's end and the burn-in time (flush 0), or also every
+    1 or 7 rounds: the same outputs as the oracle (summation order aside)."""
+    import torch
+    name, make = case
+    probs = [make(i) for i in range(2)]
+    _flush("staged %s flush=%d" % (name, flush))
+    outs = B.parrep_solve_batch(probs, cycle_log_cap=4096, histogram_staging=1,
+                                flush_period=flush)
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        assert_same(oracle.run(p, cycle_log_cap=4096), o.to_host(),
+                    what="staged %s flush=%d" % (name, flush))
