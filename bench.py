@@ -244,10 +244,13 @@ def forms(B, W, ctx, args, laws=None):
     def plain_solves(ps):
         outs = []
         t0 = time.perf_counter()
-        for p in ps:
+        for i, p in enumerate(ps):
             o = B.parrep_solve(p, ctx=ctx, cycle_log_cap=0)
             torch.cuda.synchronize()
             outs.append(o)
+            if i % 32 == 31:
+                log("forms: %d of %d plain solves, %.1f s" % (i + 1, len(ps),
+                                                              time.perf_counter() - t0))
         return time.perf_counter() - t0, [o.to_host() for o in outs]
 
     t_plain, ph = plain_solves(probs)
@@ -279,7 +282,19 @@ def forms(B, W, ctx, args, laws=None):
         emp[:n1, :n1] += h.hist
         mix[:n1, :n1] += laws[om] * p.T
         n_tv += 1
-    tv = 0.5 * float(np.abs(emp / emp.sum() - mix / mix.sum()).sum()) if n_tv else None
+    tv = tv_well = None
+    if n_tv:
+        e, m = emp / emp.sum(), mix / mix.sum()
+        tv = 0.5 * float(np.abs(e - m).sum())
+        # within each well (u > v, u <= v): the error of the sampled
+        # quasi-stationary shapes, without the noise of how the few well
+        # switches per trajectory split the time
+        g = np.arange(401)
+        upper = g[:, None] > g[None, :]
+        tv_well = 0.0
+        for wmask in (upper, ~upper):
+            ew, mw = e * wmask, m * wmask
+            tv_well += float(mw.sum()) * 0.5 * float(np.abs(ew / ew.sum() - mw / mw.sum()).sum())
     law_pool.shutdown()
 
     # served: Poisson arrivals at 0.8 x the batched capacity in requests/s
@@ -329,6 +344,7 @@ def forms(B, W, ctx, args, laws=None):
         "plain_sample": "all %d instances solved one at a time" % len(probs),
         "batched_equals_plain": batch_equal,
         "tv_pooled_toggle_omega_le_50": tv,
+        "tv_within_wells_toggle_omega_le_50": tv_well,
         "tv_instances": n_tv,
         "served": {
             "requests": len(infos), "arrival_rate_per_s": rate,
@@ -389,6 +405,10 @@ def main():
     ap.add_argument("--T", type=float, default=2e4)
     ap.add_argument("--rpl", type=int, default=0, help="replicas per lane (0 = library choice)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = library)")
+    ap.add_argument("--staging", type=int, default=0, choices=(-1, 0, 1),
+                    help="parallel-step histogram staging in LDS (0 = library / autotuned)")
+    ap.add_argument("--flush-period", type=int, default=0,
+                    help="staged: also flush every this many rounds")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU baseline: start trajectories for this long")
     ap.add_argument("--cpu-T", type=float, default=2e4,
@@ -450,13 +470,16 @@ def main():
         probs = [W.genetic_switch_problem(seed=0, instance_id=i, T=args.T)
                  for i in range(args.instances)]
     shape = None
-    if toggle and args.rpl == 0 and args.waves == 0 and not args.no_autotune:
-        # untimed: pick the launch shape for R = 1024 on copies cut to 2e6 events
+    if toggle and args.rpl == 0 and args.waves == 0 and args.staging == 0 and not args.no_autotune:
+        # untimed: pick the launch shape and histogram staging for R = 1024 on
+        # copies with the horizon cut to T/10 (the same mix of steps: every
+        # cycle dephases all replicas, the parallel step credits ~T a0 events)
         t = time.perf_counter()
-        shape = B.parrep_autotune(probs[0].replace(instance_id=1 << 30), instances=1024,
-                                  trial_events=2_000_000, ctx=ctx)
-        log("autotune: replicas_per_lane=%d waves=%d (%.1f s)" % (shape[0], shape[1],
-                                                                   time.perf_counter() - t))
+        shape = B.parrep_autotune(probs[0].replace(instance_id=1 << 30, T=args.T / 10,
+                                                   t_burn=args.T / 20),
+                                  instances=1024, trial_events=1 << 40, ctx=ctx)
+        log("autotune: replicas_per_lane=%d waves=%d staging=%d flush=%d (%.1f s)"
+            % (shape + (time.perf_counter() - t,)))
     outs = [B.Outputs(ctx, p, cycle_log_cap=0, phase_clock=args.phase_clock) for p in probs]
     ev_b = torch.cuda.Event(enable_timing=True)
     ev_a = torch.cuda.Event(enable_timing=True)
@@ -467,7 +490,8 @@ def main():
     # step enqueues setup / zero / the instance kernels / finalize on them, with
     # the inputs already resident, and the two events on the stream around the
     # instance kernels.
-    plan = B.Plan(probs, ctx=ctx, outputs=outs, replicas_per_lane=args.rpl, waves=args.waves)
+    plan = B.Plan(probs, ctx=ctx, outputs=outs, replicas_per_lane=args.rpl, waves=args.waves,
+                  histogram_staging=args.staging, flush_period=args.flush_period)
     stream = torch.cuda.current_stream()
 
     for i in range(args.warmup):
@@ -521,8 +545,12 @@ def main():
                          "T/2, FIM+RER of 8 parameters; %d independent trajectories per step"
                          % (args.T, args.instances)),
             "instances": args.instances,
-            "launch_shape": ({"replicas_per_lane": shape[0], "waves": shape[1], "autotuned": True}
-                             if shape else {"replicas_per_lane": args.rpl, "waves": args.waves}),
+            "launch_shape": ({"replicas_per_lane": shape[0], "waves": shape[1],
+                              "histogram_staging": shape[2], "flush_period": shape[3],
+                              "autotuned": True}
+                             if shape else {"replicas_per_lane": args.rpl, "waves": args.waves,
+                                            "histogram_staging": args.staging,
+                                            "flush_period": args.flush_period}),
             "replicas": probs[0].R,
             "horizon": args.T,
         },

@@ -206,6 +206,15 @@ typedef struct {
     int32_t chunk_rounds[2];    /* spread runs: dephasing and parallel-step chunk
                                    lengths in rounds (0 = 512 and 64; the second <= 64) */
     int32_t barrier_wait_us;    /* spread runs: longest wait at a meeting point       */
+    int32_t histogram_staging;  /* parallel-step credits (<= 2 species, <= 4 reactions):
+                                   0 = library choice (the autotuned setting, else off),
+                                   -1 = one HBM atomic per credit, 1 = credits at states
+                                   in a 1024-bin tile of the box (placed per parallel
+                                   step on the replicas' mean) go to LDS and are flushed
+                                   with one atomic per visited bin; either setting fixes
+                                   the shape as replicas_per_lane and waves do          */
+    int32_t flush_period;       /* staged: also flush every this many rounds (0 = only
+                                   at the step's end and at the burn-in time)          */
 } parrep_launch;
 
 /* Create a context on a HIP device: it owns the scratch arena and the
@@ -315,9 +324,11 @@ void parrep_plan_destroy(parrep_plan* plan);
 
 /* Launch-shape autotuner: times `instances` copies of prob (instance ids
  * prob->instance_id + i, each cut to trial_events events) for every compiled
- * shape that holds prob->R replicas (up to 16x), keeps the fastest for R's
- * bucket (the next power of two >= max(R, 64)), this species count and
- * reaction class, and returns it in *chosen.  scratch: device buffers that
+ * shape that holds prob->R replicas (up to 16x), and for the narrow kernels
+ * every histogram staging setting (off, flushed at the step's end, flushed
+ * every 64 rounds), keeps the fastest for R's bucket (the next power of two
+ * >= max(R, 64)), this species count and reaction class, and returns it in
+ * *chosen.  scratch: device buffers that
  * all trial instances overwrite (their values are meaningless).  Blocking. */
 int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
                     int32_t instances, int64_t trial_events, const parrep_result* scratch,

@@ -67,7 +67,8 @@ class Launch(C.Structure):
     _fields_ = [("replicas_per_lane", C.c_int32), ("waves", C.c_int32),
                 ("event_before", C.c_void_p), ("event_after", C.c_void_p),
                 ("workgroups", C.c_int32), ("chunk_rounds", C.c_int32 * 2),
-                ("barrier_wait_us", C.c_int32)]
+                ("barrier_wait_us", C.c_int32), ("histogram_staging", C.c_int32),
+                ("flush_period", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -325,7 +326,8 @@ def parrep_solve_batch(problems: Sequence[W.Problem], ctx: Optional[Context] = N
                        stream=None, replicas_per_lane: int = 0, waves: int = 0,
                        cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None,
                        events=None, workgroups: int = 0, chunk_rounds=(0, 0),
-                       barrier_wait_us: int = 0) -> List[Outputs]:
+                       barrier_wait_us: int = 0, histogram_staging: int = 0,
+                       flush_period: int = 0) -> List[Outputs]:
     """Many independent solves in one launch; returns per-instance device outputs.
     workgroups, chunk_rounds, barrier_wait_us: see parrep_launch (spreading a
     single instance over workgroups)."""
@@ -336,7 +338,7 @@ def parrep_solve_batch(problems: Sequence[W.Problem], ctx: Optional[Context] = N
     ps = (Problem * n)(*[problem_struct(p) for p in problems])
     rs = (Result * n)(*[o.struct() for o in outs])
     la = Launch(replicas_per_lane, waves, None, None, workgroups,
-                (C.c_int32 * 2)(*chunk_rounds), barrier_wait_us)
+                (C.c_int32 * 2)(*chunk_rounds), barrier_wait_us, histogram_staging, flush_period)
     if events is not None:  # (before, after) torch.cuda.Event pair, already created
         la.event_before, la.event_after = events[0].cuda_event, events[1].cuda_event
     _check(lib().parrep_solve_batch(ctx.h, n, nets, ps, rs, C.byref(la), _stream_ptr(stream)))
@@ -443,7 +445,8 @@ class Plan:
 
     def __init__(self, problems: Sequence[W.Problem], ctx: Optional[Context] = None,
                  cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None,
-                 replicas_per_lane: int = 0, waves: int = 0):
+                 replicas_per_lane: int = 0, waves: int = 0, histogram_staging: int = 0,
+                 flush_period: int = 0):
         self.ctx = ctx or context()
         n = len(problems)
         self.problems = list(problems)
@@ -453,6 +456,7 @@ class Plan:
         ps = (Problem * n)(*[problem_struct(p) for p in problems])
         rs = (Result * n)(*[o.struct() for o in self.outputs])
         la = Launch(replicas_per_lane, waves, None, None)
+        la.histogram_staging, la.flush_period = histogram_staging, flush_period
         h = C.c_void_p()
         _check(lib().parrep_plan_create(self.ctx.h, n, nets, ps, rs, C.byref(la), C.byref(h)))
         self.h = h
@@ -487,8 +491,10 @@ class Plan:
 
 def parrep_autotune(p: W.Problem, instances: int = 1024, trial_events: int = 2_000_000,
                     ctx: Optional[Context] = None):
-    """Time every compiled launch shape on copies of p; returns (replicas_per_lane, waves),
-    which later batches of the same replica-count bucket then use."""
+    """Time every compiled launch shape (and histogram staging setting) on
+    copies of p; returns (replicas_per_lane, waves, histogram_staging,
+    flush_period), which later batches of the same replica-count bucket then
+    use."""
     ctx = ctx or context()
     scratch = Outputs(ctx, p, cycle_log_cap=0)
     ps = problem_struct(p)
@@ -496,7 +502,7 @@ def parrep_autotune(p: W.Problem, instances: int = 1024, trial_events: int = 2_0
     la = Launch()
     _check(lib().parrep_autotune(ctx.h, ctx.net(p.net), C.byref(ps), instances, trial_events,
                                  C.byref(rs), C.byref(la)))
-    return la.replicas_per_lane, la.waves
+    return la.replicas_per_lane, la.waves, la.histogram_staging, la.flush_period
 
 
 class Server:

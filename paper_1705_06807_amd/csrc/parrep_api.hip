@@ -95,6 +95,7 @@ void fill_inst(DevInst& d, const parrep_net* net, const parrep_problem* p, int64
         d.rer_eps[k] = (k < d.net.n_params && p->use_rer) ? p->rer_eps[k] : 0.0;
     }
     d.use_rer = p->use_rer ? 1 : 0;
+    d.stage_flush = -1;
     d.decorr_mode = p->decorr_mode;
     d.dephase_mode = p->dephase_mode;
     d.R = p->R;
@@ -290,7 +291,8 @@ LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m, bool sparse) {
     if (sparse && R > 64 && R <= 256) return LaunchShape{1, 4, nsc, mc};
     auto it = ctx->tuned.find(std::make_tuple(shape_bucket(R), nsc, mc));
     if (it != ctx->tuned.end()) {
-        LaunchShape s{it->second.first, it->second.second, nsc, mc};
+        LaunchShape s{std::get<0>(it->second), std::get<1>(it->second), nsc, mc};
+        s.stage_flush = std::get<2>(it->second);
         if ((int64_t)s.rpl * s.waves * 64 >= R) return s;
     }
     return choose_shape(R, nsc, mc);
@@ -329,9 +331,13 @@ std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
         groups.back().count += 1;
     }
     for (Group& g : groups) {
+        // staging applies to the narrow kernels only
+        if (!narrow_kernel(g.shape.ns, g.shape.m)) g.shape.stage_flush = -1;
         int need = 0;
-        for (int i = g.first; i < g.first + g.count; ++i)
+        for (int i = g.first; i < g.first + g.count; ++i) {
             need = std::max(need, table_lds_need(insts[i], g.shape));
+            insts[i].stage_flush = g.shape.stage_flush;
+        }
         g.tab_lds = table_lds_doubles(g.shape, need);
     }
     if (order) *order = ord;
@@ -642,11 +648,17 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
     hipEvent_t ev_a = launch ? (hipEvent_t)launch->event_after : nullptr;
     LaunchShape forced{};
     const bool spread = launch && launch->workgroups > 1;
-    const bool force = !spread && launch && (launch->replicas_per_lane > 0 || launch->waves > 0);
+    if (launch && (launch->histogram_staging < -1 || launch->histogram_staging > 1 ||
+                   launch->flush_period < 0))
+        return fail(PARREP_EINVAL, "histogram_staging must be -1, 0 or 1 and flush_period >= 0");
+    const bool force = !spread && launch &&
+                       (launch->replicas_per_lane > 0 || launch->waves > 0 ||
+                        launch->histogram_staging != 0);
     if (force) {
         forced = choose_shape(maxR, maxS, kMaxM);
         forced.rpl = launch->replicas_per_lane > 0 ? launch->replicas_per_lane : forced.rpl;
         forced.waves = launch->waves > 0 ? launch->waves : forced.waves;
+        forced.stage_flush = launch->histogram_staging > 0 ? std::max(0, launch->flush_period) : -1;
         if ((int64_t)forced.rpl * forced.waves * 64 < maxR)
             return fail(PARREP_EINVAL, "launch shape holds fewer replicas than R");
         if (!shape_supported(forced)) return fail(PARREP_EUNSUPPORTED, "launch shape not compiled in");

@@ -70,11 +70,18 @@ int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
         maxS = std::max(maxS, (int)nets[i]->net.n_species);
     }
     LaunchShape forced{};
-    const bool force = launch && (launch->replicas_per_lane > 0 || launch->waves > 0);
+    if (launch && (launch->histogram_staging < -1 || launch->histogram_staging > 1 ||
+                   launch->flush_period < 0)) {
+        delete p;
+        return fail(PARREP_EINVAL, "histogram_staging must be -1, 0 or 1 and flush_period >= 0");
+    }
+    const bool force = launch && (launch->replicas_per_lane > 0 || launch->waves > 0 ||
+                                  launch->histogram_staging != 0);
     if (force) {
         forced = choose_shape(maxR, maxS, kMaxM);
         forced.rpl = launch->replicas_per_lane > 0 ? launch->replicas_per_lane : forced.rpl;
         forced.waves = launch->waves > 0 ? launch->waves : forced.waves;
+        forced.stage_flush = launch->histogram_staging > 0 ? std::max(0, launch->flush_period) : -1;
         int rc = PARREP_OK;
         if ((int64_t)forced.rpl * forced.waves * 64 < maxR)
             rc = fail(PARREP_EINVAL, "launch shape holds fewer replicas than R");
@@ -229,9 +236,15 @@ int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem
     float best = -1.0f;
     LaunchShape best_s{};
     const int ropts[4] = {1, 4, 16, 64}, wopts[3] = {1, 4, 16};
+    // histogram staging (narrow kernels): off, flushed at the step's end, or
+    // also every 64 rounds
+    const int sopts[3] = {-1, 0, 64};
+    const int nst = narrow_kernel(nsc, mc) ? 3 : 1;
     for (int a = 0; a < 4 && !rc; ++a)
-        for (int b = 0; b < 3 && !rc; ++b) {
+        for (int b = 0; b < 3 && !rc; ++b)
+        for (int c = 0; c < nst && !rc; ++c) {
             LaunchShape s{ropts[a], wopts[b], nsc, mc};
+            s.stage_flush = sopts[c];
             const int64_t cap = (int64_t)s.rpl * s.waves * 64;
             if (cap < R || cap > 16 * (int64_t)std::max(R, 64) || !shape_supported(s)) continue;
             // all trial instances write the same (scratch) outputs: only the
@@ -268,10 +281,13 @@ int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem
     if (best < 0.0f) return fail(PARREP_EUNSUPPORTED, "no compiled launch shape holds R replicas");
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->tuned[std::make_tuple(shape_bucket(R), nsc, mc)] = std::make_pair(best_s.rpl, best_s.waves);
+        ctx->tuned[std::make_tuple(shape_bucket(R), nsc, mc)] =
+            std::make_tuple(best_s.rpl, best_s.waves, best_s.stage_flush);
     }
     chosen->replicas_per_lane = best_s.rpl;
     chosen->waves = best_s.waves;
+    chosen->histogram_staging = best_s.stage_flush >= 0 ? 1 : -1;
+    chosen->flush_period = std::max(0, best_s.stage_flush);
     chosen->event_before = nullptr;
     chosen->event_after = nullptr;
     return PARREP_OK;

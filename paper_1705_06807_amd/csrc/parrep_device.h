@@ -766,6 +766,99 @@ __device__ __forceinline__ bool credit_event(const DevInst* __restrict__ I, cons
 
 
 // ---------------------------------------------------------------------------
+// Histogram staging tile (LDS)
+// ---------------------------------------------------------------------------
+// Bins [a0, a0 + n0) x [a1, a1 + n1) of the histogram (absolute states; one
+// species: n1 = 1), row-major in LDS; kept for one parallel step.
+struct TileWin {
+    int a0, a1, n0, n1;
+};
+
+template <int NS>
+__device__ __forceinline__ int tile_slot(const TileWin& t, const int (&x)[NS]) {
+    const int d0 = x[0] - t.a0;
+    const int d1 = NS > 1 ? x[NS > 1 ? 1 : 0] - t.a1 : 0;
+    return ((unsigned)d0 < (unsigned)t.n0 && (unsigned)d1 < (unsigned)t.n1) ? d0 * t.n1 + d1 : -1;
+}
+
+// Add the tile to hist (before the burn-in time) or hist_w (after), one
+// atomic per visited bin, consecutive threads on consecutive bins of a row,
+// and clear it.  The whole workgroup takes part.
+template <int NS>
+__device__ __attribute__((noinline)) void flush_tile(const DevInst* __restrict__ I, double* tile, const TileWin& t,
+                           bool win, int tid, int nthreads) {
+    __syncthreads();
+    double* tgt = win ? I->hist_w : I->hist;
+    const int64_t s0 = I->hist_stride[0];
+    const int64_t s1 = NS > 1 ? I->hist_stride[1] : 0;
+    const int64_t base = (int64_t)(t.a0 - I->hist_lo[0]) * s0 +
+                         (NS > 1 ? (int64_t)(t.a1 - I->hist_lo[1]) * s1 : 0);
+    const int n = t.n0 * t.n1;
+    for (int i = tid; i < n; i += nthreads) {
+        const double v = tile[i];
+        if (v != 0.0) {
+            const int d0 = i / t.n1, d1 = i - d0 * t.n1;
+            atomicAdd(&tgt[base + d0 * s0 + d1 * s1], v);
+            tile[i] = 0.0;
+        }
+    }
+    __syncthreads();
+}
+
+// Place the tile for a parallel step on the replicas' states: centred on
+// their mean, n1 = 16 bins along the second species when the first spreads
+// more (64 otherwise), clamped to the histogram box.  Every thread returns
+// the same window (the partial sums are combined in one order).
+template <int NS, int RPL, int WAVES>
+__device__ __attribute__((noinline)) TileWin place_tile(const DevInst* __restrict__ I, double* tile, const int (&Y)[RPL][NS],
+                              int R, int tid, int lane, int wid) {
+    constexpr int B = 64 * WAVES;
+    constexpr int kUK = RPL <= 16 ? RPL : 1;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll kUK
+    for (int k = 0; k < RPL; ++k) {
+        if (k * B + tid < R) {
+#pragma unroll
+            for (int i = 0; i < NS && i < 2; ++i) {
+                const double x = (double)Y[k][i];
+                s[i] += x;
+                s[2 + i] += x * x;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int off = 32; off >= 1; off >>= 1) s[q] += __shfl_xor(s[q], off);
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) tile[wid * 4 + q] = s[q];
+    __syncthreads();
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < WAVES; ++w)
+        for (int q = 0; q < 4; ++q) S[q] += tile[w * 4 + q];
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) tile[wid * 4 + q] = 0.0;
+    const double m0 = S[0] / R, m1 = S[1] / R;
+    const double v0 = S[2] / R - m0 * m0, v1 = S[3] / R - m1 * m1;
+    const int nb0 = I->hist_nb[0], nb1 = NS > 1 ? I->hist_nb[1] : 1;
+    int n1 = NS > 1 ? min(nb1, v0 >= v1 ? 16 : 64) : 1;
+    const int n0 = min(nb0, kTileDoubles / n1);
+    if (NS > 1) n1 = min(nb1, kTileDoubles / n0);
+    const int c0 = (int)floor(m0) - I->hist_lo[0] - n0 / 2;
+    const int c1 = NS > 1 ? (int)floor(m1) - I->hist_lo[1] - n1 / 2 : 0;
+    TileWin t;
+    t.n0 = n0;
+    t.n1 = n1;
+    t.a0 = I->hist_lo[0] + max(0, min(c0, nb0 - n0));
+    t.a1 = NS > 1 ? I->hist_lo[1] + max(0, min(c1, nb1 - n1)) : 0;
+    t.a0 = __builtin_amdgcn_readfirstlane(t.a0);
+    t.a1 = __builtin_amdgcn_readfirstlane(t.a1);
+    t.n0 = __builtin_amdgcn_readfirstlane(t.n0);
+    t.n1 = __builtin_amdgcn_readfirstlane(t.n1);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
 // Workgroup communication
 // ---------------------------------------------------------------------------
 template <int E, int WAVES>
@@ -1321,6 +1414,23 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         int Kx = 0;
         double tauk[RPL];
         uint32_t dxk[RPL];
+        // Histogram staging (narrow kernels, full solves): credits of whole
+        // rounds at states inside a tile of the histogram box go to an LDS
+        // copy of that tile (kTileDoubles bins, after the tables; the
+        // launcher reserved it) instead of one HBM atomic each; the tile is
+        // flushed with one atomic per visited bin.  Decided here, so that
+        // nothing of it is live during the other steps.
+        const int stage_flush = I->stage_flush;
+        const bool stage = narrow_kernel(NS, M) && accum && stage_flush >= 0;
+        double* tile = ltab + tab_lds;
+        TileWin tw{0, 0, 0, 0};
+        bool tile_win = false;  // the tile holds time after the burn-in time
+        int since = 0;          // rounds credited to the tile since its last flush
+        if (stage) {
+            for (int i = tid; i < kTileDoubles; i += B) tile[i] = 0.0;
+            tw = place_tile<NS, RPL, WAVES>(I, tile, Y, R, tid, lane, wid);
+            tile_win = fx_ge(C, tbq);
+        }
         for (;;) {
             if (round3 >= budget3) {
                 outcome = -1;
@@ -1372,10 +1482,30 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             if (!boundary) {
                 if (accum) {
                     const bool win = fx_ge(C, tbq);
+                    if (stage) {
+                        // the tile holds one side of the burn-in time; flush it
+                        // when that side changes and every stage_flush rounds
+                        if (win != tile_win || (stage_flush > 0 && since >= stage_flush)) {
+                            flush_tile<NS>(I, tile, tw, tile_win, tid, B);
+                            tile_win = win;
+                            since = 0;
+                        }
 #pragma unroll kUK
-                    for (int k = 0; k < RPL; ++k) {
-                        const int r = k * B + tid;
-                        if (r < K) add_credit<NS>(I, Y[k], tauk[k], win ? tauk[k] : 0.0);
+                        for (int k = 0; k < RPL; ++k) {
+                            const int r = k * B + tid;
+                            if (r < K) {
+                                const int ts = tile_slot<NS>(tw, Y[k]);
+                                if (ts >= 0) atomicAdd(&tile[ts], tauk[k]);
+                                else add_credit<NS>(I, Y[k], tauk[k], win ? tauk[k] : 0.0);
+                            }
+                        }
+                        ++since;
+                    } else {
+#pragma unroll kUK
+                        for (int k = 0; k < RPL; ++k) {
+                            const int r = k * B + tid;
+                            if (r < K) add_credit<NS>(I, Y[k], tauk[k], win ? tauk[k] : 0.0);
+                        }
                     }
                 }
                 C = Cend;
@@ -1463,6 +1593,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             for (int k = 0; k < RPL; ++k) apply_dx<NS>(Y[k], dxk[k]);
         }
         __syncthreads();
+        if (stage) flush_tile<NS>(I, tile, tw, tile_win, tid, B);
         if (mode == kModeParallelOnly) {
             if (tid == 0) {
                 I->hook_i64[0] = outcome == 1 ? round3 : -1;

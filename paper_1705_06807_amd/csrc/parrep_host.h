@@ -22,8 +22,8 @@ struct parrep_ctx {
     // side by side; created on first use.
     std::vector<hipStream_t> aux;
     // Autotuned launch shapes: (replica-count bucket, species, reaction class)
-    // -> (replicas per lane, waves).
-    std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
+    // -> (replicas per lane, waves, histogram staging: DevInst::stage_flush).
+    std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> tuned;
     // Device address of this device's fixed scratch array (parrep_solve_noalloc).
     char* noalloc_scratch = nullptr;
     double wall_hz = 1e8;  // rate of the device's constant wall clock

@@ -45,6 +45,8 @@ struct SpillSlot {
     double w;
 };
 constexpr int kSpillCap = 2048;
+// Bins of the LDS histogram tile of the instance kernel (8 KiB).
+constexpr int kTileDoubles = 1024;
 
 // Exchange area of one instance spread over several workgroups (the wide
 // instance kernel): a grid barrier, the chunk results the workgroups agree
@@ -107,6 +109,10 @@ struct DevInst {
     int32_t wide_s2, wide_s3;   // chunk lengths (rounds) of dephasing and parallel step
     int64_t wide_wait_ticks;    // wall-clock ticks a workgroup waits at a grid barrier
     int32_t wide_waves, wide_rpl;  // waves of the launch and replicas per lane (0: not wide)
+    // parallel-step histogram staging in LDS (narrow kernels): -1 off (one
+    // HBM atomic per credit), 0 flush at the end of the step and at the
+    // burn-in time, P > 0 also every P rounds
+    int32_t stage_flush, reserved2;
     // test-hook outputs (unused by full solves)
     int32_t* hook_states;   // dephase-only: output states; parallel-only: input states
     int32_t* hook_exit;     // parallel-only: exit state
@@ -154,8 +160,9 @@ __host__ __device__ constexpr bool narrow_kernel(int ns, int m) { return ns <= 2
 
 struct LaunchShape {
     int rpl, waves, ns;
-    int m;         // reactions (the kernel is specialised for m <= 4 and m <= 8)
-    int wide = 0;  // > 0: one instance over this many workgroups (4 waves each)
+    int m;                 // reactions (the kernel is specialised for m <= 4 and m <= 8)
+    int wide = 0;          // > 0: one instance over this many workgroups (4 waves each)
+    int stage_flush = -1;  // histogram staging of the group's instances (DevInst::stage_flush)
 };
 
 // Launchers (parrep_kernels.hip).

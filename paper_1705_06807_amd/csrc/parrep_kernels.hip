@@ -427,7 +427,7 @@ LaunchShape choose_shape(int R, int ns, int m) {
 
 #define PARREP_DECL(NSv, Wv)                                                                  \
     hipError_t launch_instance_ns##NSv##_w##Wv(const DevInst*, int, int, int, int, uint32_t,     \
-                                               int64_t, int, hipStream_t);
+                                               int64_t, int, int, hipStream_t);
 PARREP_DECL(1, 1) PARREP_DECL(1, 4) PARREP_DECL(1, 16)
 PARREP_DECL(2, 1) PARREP_DECL(2, 4) PARREP_DECL(2, 16)
 PARREP_DECL(4, 1) PARREP_DECL(4, 4) PARREP_DECL(4, 16)
@@ -440,7 +440,8 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mo
 #define PARREP_GO(NSv, Wv)                                                                    \
     if (s.ns == NSv && s.waves == Wv)                                                         \
         return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.m, s.rpl, mode, hook_cycle,  \
-                                               hook_max_rounds, tab_lds, stream);
+                                               hook_max_rounds, tab_lds, s.stage_flush >= 0,   \
+                                               stream);
     PARREP_GO(1, 1) PARREP_GO(1, 4) PARREP_GO(1, 16)
     PARREP_GO(2, 1) PARREP_GO(2, 4) PARREP_GO(2, 16)
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
@@ -480,8 +481,10 @@ int table_lds_need(const DevInst& d, LaunchShape s) {
 }
 
 int table_lds_doubles(LaunchShape s, int max_need) {
-    // the wide kernel runs one workgroup per CU and exchanges through HBM
-    const size_t xb = s.wide ? 0 : xbuf_lds_bytes(s.rpl, s.waves, s.ns);
+    // the wide kernel runs one workgroup per CU and exchanges through HBM;
+    // a staging tile takes 8 KiB more
+    size_t xb = s.wide ? 0 : xbuf_lds_bytes(s.rpl, s.waves, s.ns);
+    if (!s.wide && s.stage_flush >= 0) xb += kTileDoubles * 8;
     // leaves room for the static LDS of the kernel (24 KB more of it with 64
     // replicas per lane: the survivor masks and counts of 1024 slots)
     const size_t budget = (s.rpl == 64 ? 32 : 56) * 1024;

@@ -102,8 +102,10 @@ def test_plan_update(B):
 def test_autotune_then_parity(B, oracle):
     import torch
     p = W.c2_toggle(seed=4, omega=5.0, R=200, T=40.0, t_cp=1.0).replace(hist_hi=(40, 40))
-    rpl, waves = B.parrep_autotune(p, instances=64, trial_events=50000)
-    _flush("autotuned shape for R=200: rpl=%d waves=%d" % (rpl, waves))
+    rpl, waves, staging, flush = B.parrep_autotune(p, instances=64, trial_events=50000)
+    _flush("autotuned shape for R=200: rpl=%d waves=%d staging=%d flush=%d"
+           % (rpl, waves, staging, flush))
+    assert staging in (-1, 1) and flush >= 0
     assert rpl * waves * 64 >= 200
     probs = [p.replace(instance_id=i) for i in range(3)]
     outs = B.parrep_solve_batch(probs, cycle_log_cap=4096)
