@@ -333,6 +333,24 @@ std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
     for (Group& g : groups) {
         // staging applies to the narrow kernels only
         if (!narrow_kernel(g.shape.ns, g.shape.m)) g.shape.stage_flush = -1;
+        // a compiled specialisation when every instance of the group fits
+        // it: the species-map kernel (its fixed-stride tables must also fit
+        // the LDS budget) or the network-descriptor kernel
+        g.shape.spec = -1;
+        const bool nk = narrow_kernel(g.shape.ns, g.shape.m);
+        auto spec_of = [&](const DevInst& d) -> long long {
+            return nk ? (long long)species_map(d, g.shape) : network_desc(d, g.shape);
+        };
+        long long spec = spec_of(insts[g.first]);
+        for (int i = g.first; i < g.first + g.count && spec >= 0; ++i)
+            if (spec_of(insts[i]) != spec) spec = -1;
+        if (spec >= 0 && nk) {
+            LaunchShape t = g.shape;
+            t.spec = spec;
+            const int need = table_lds_need(insts[g.first], t);
+            if (table_lds_doubles(t, need) < need) spec = -1;
+        }
+        g.shape.spec = spec;
         int need = 0;
         for (int i = g.first; i < g.first + g.count; ++i) {
             need = std::max(need, table_lds_need(insts[i], g.shape));
@@ -423,6 +441,7 @@ int apply_wide(parrep_ctx* ctx, std::vector<DevInst>& insts, std::vector<Group>&
     g.shape.rpl = rpl;
     g.shape.waves = 4;
     g.shape.wide = G;
+    g.shape.spec = -1;
     g.tab_lds = table_lds_doubles(g.shape, table_lds_need(d, g.shape));
     d.wide_waves = 4 * G;
     d.wide_rpl = rpl;

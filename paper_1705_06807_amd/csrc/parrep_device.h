@@ -30,6 +30,7 @@
 
 #include <climits>
 #include <type_traits>
+#include <utility>
 
 namespace parrep {
 namespace dev {
@@ -347,15 +348,19 @@ struct TabLayout {
     int Ls;  // narrow kernels: the common length
 };
 
-template <int M, bool kAll>
+template <int M, bool kAll, long long SPEC = -1>
 __device__ __forceinline__ TabLayout<M> tab_layout(const DevInst* __restrict__ I, int avail) {
     TabLayout<M> t;
     if (kAll) {
         const int L = I->tab_L;
         t.Ls = L < avail / M ? L : avail / M;
+        // a compiled species map fixes the row stride, so that a lane forms
+        // one address per species and every row is an immediate offset
+        const int stride = SPEC >= 0 ? kMapStride : t.Ls;
+        if (SPEC >= 0 && t.Ls > kMapStride) t.Ls = kMapStride;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            t.off[j] = j * t.Ls;
+            t.off[j] = j * stride;
             t.len[j] = t.Ls;
         }
         return t;
@@ -532,6 +537,67 @@ __device__ __forceinline__ void lams_general(const HotNet<M>& h, const DevInst* 
     }
 }
 
+// lambda_j(x) of reaction J under the compiled network descriptor D: the
+// cases of lam_general with kind, species and tail constants, so that the
+// state is read by constant indices (registers, not an indexed private
+// array) and the kind dispatch leaves the chain.  Reactions past the
+// descriptor's count are the padding (lambda = 0).
+template <int NS, int M, long long D, int J>
+__device__ __forceinline__ double lam_desc(const HotNet<M>& h, const double* __restrict__ ltab,
+                                           const int (&x)[NS], uint32_t* need) {
+    constexpr uint32_t meta = desc_meta(D, J);
+    constexpr uint32_t kind = meta & 3u;
+    constexpr int sp = (int)((meta >> 2) & 3u), ts = (int)((meta >> 6) & 3u);
+    constexpr uint32_t o1 = (meta >> 4) & 3u, to = (meta >> 8) & 3u;
+    static_assert(sp < NS && ts < NS, "descriptor species beyond the kernel's");
+    if constexpr (J >= desc_count(D)) {
+        return 0.0;
+    } else if constexpr (kind == kRxConst) {
+        return h.k[J];
+    } else if constexpr (kind == kRxDirect) {
+        *need |= 1u << J;
+        return 0.0;
+    } else {
+        const int xs = x[sp];
+        double lam;
+        if constexpr (kind == kRxFall) {
+            lam = h.k[J] * fall12(xs, o1);
+        } else {
+            const bool in = (unsigned)xs < (unsigned)h.len[J];
+            lam = ltab[h.off[J] + (in ? xs : 0)];
+            if (!in) *need |= 1u << J;  // replaced by the formula
+        }
+        if constexpr (to != 0u) lam = lam * fall12(x[ts], to);
+        return lam;
+    }
+}
+
+template <int NS, int M, long long D, int... J>
+__device__ __forceinline__ void lams_desc_seq(const HotNet<M>& h, const double* __restrict__ ltab,
+                                              const int (&x)[NS], double (&lam)[M],
+                                              uint32_t* need, std::integer_sequence<int, J...>) {
+    ((lam[J] = lam_desc<NS, M, D, J>(h, ltab, x, need)), ...);
+}
+
+// All M propensities under descriptor D (the formula for direct reactions
+// and for table states the LDS does not hold, as in lams_general).
+template <int NS, int M, long long D>
+__device__ __forceinline__ void lams_desc(const HotNet<M>& h, const DevInst* __restrict__ I,
+                                          const double* __restrict__ ltab, const int (&x)[NS],
+                                          double (&lam)[M]) {
+    uint32_t need = 0;
+    lams_desc_seq<NS, M, D>(h, ltab, x, lam, &need, std::make_integer_sequence<int, M>{});
+    if (need) {
+#pragma unroll 1
+        for (int j = 0; j < M; ++j) {
+            if (!((need >> j) & 1u)) continue;
+            const double v = lambda_formula<NS>(I, j, x);
+#pragma unroll
+            for (int jj = 0; jj < M; ++jj) lam[jj] = jj == j ? v : lam[jj];
+        }
+    }
+}
+
 // lambda_j(x) in the narrow kernels off the fast path: the table when the
 // lane's state is inside every table, else the constant or the formula.
 template <int NS, int M>
@@ -540,9 +606,24 @@ __device__ __forceinline__ double lam_narrow(const HotNet<M>& h, const DevInst* 
                                              const int (&x)[NS], int j, bool inr) {
     const uint32_t kind = j < I->net.n_reactions ? I->jmeta[j] & 3u : (uint32_t)kRxConst;
     if (kind != kRxDirect && inr)
-        return ltab[j * h.Ls + pick<NS>(x, (int)((h.species >> (2 * j)) & 3u))];
+        return ltab[h.off[j] + pick<NS>(x, (int)((h.species >> (2 * j)) & 3u))];
     if (kind == kRxConst) return I->k[j];
     return lambda_formula<NS>(I, j, x);
+}
+
+// n / a for the waiting time: n times 1/a, the reciprocal refined from the
+// hardware approximation by two Newton steps.  Within 1.5 ulp of the exact
+// quotient for the positive, finite a0 of a Gillespie step (the IEEE
+// division takes four more instructions for its range scaling and its
+// correctly rounded result); with the -log routine's own error the device's
+// tau is within 3.5 ulp of the oracle's log(u)/a0.
+__device__ __forceinline__ double waiting_time(double n, double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-a, r, 1.0);
+    r = fma(r, e, r);
+    return n * r;
 }
 
 // One Gillespie event at x (the "generate tau and J" step of Alg. 1):
@@ -553,7 +634,7 @@ __device__ __forceinline__ double lam_narrow(const HotNet<M>& h, const DevInst* 
 // kernels read every reaction from a table and take the formula for the
 // whole wave when a lane's state is outside the tables (rare) or a reaction
 // is direct; the general kernels decide per reaction.
-template <int NS, int M>
+template <int NS, int M, long long SPEC = -1>
 __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
                                                     const DevInst* __restrict__ I,
                                                     const double* __restrict__ ltab,
@@ -568,12 +649,24 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
 #pragma unroll
         for (int i = 0; i < NS; ++i) inr = inr && (unsigned)x[i] < (unsigned)h.Ls;
         if (__builtin_expect(__ballot(!inr) == 0ull && !h.any_direct, 1)) {
+            if constexpr (SPEC >= 0 && kNarrowK) {
+                // reaction j reads its row at the state of species (SPEC >> j) & 1
+                const double* t0 = ltab + x[0];
+                const double* t1 = ltab + x[NS > 1 ? 1 : 0];
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
-                const double lam = ltab[j * h.Ls + xs];
-                s = j == 0 ? lam : s + lam;  // 0 + lam_1 = lam_1 (lam_1 >= 0)
-                cum[j] = s;
+                for (int j = 0; j < M; ++j) {
+                    const double lam = (((SPEC >> j) & 1) ? t1 : t0)[j * kMapStride];
+                    s = j == 0 ? lam : s + lam;
+                    cum[j] = s;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    const int xs = pick<NS>(x, (int)((h.species >> (2 * j)) & 3u));
+                    const double lam = ltab[j * h.Ls + xs];
+                    s = j == 0 ? lam : s + lam;  // 0 + lam_1 = lam_1 (lam_1 >= 0)
+                    cum[j] = s;
+                }
             }
         } else {
 #pragma unroll
@@ -582,6 +675,16 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
                 s = j == 0 ? lam : s + lam;
                 cum[j] = s;
             }
+        }
+    } else if constexpr (SPEC >= 0) {
+        // the padding past the descriptor's count adds nothing (s + 0.0 = s
+        // for the non-negative partial sums), so it is left out
+        double lam[M];
+        lams_desc<NS, M, SPEC>(h, I, ltab, x, lam);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            s = j == 0 ? lam[j] : (j < desc_count(SPEC) ? s + lam[j] : s);
+            cum[j] = s;
         }
     } else {
         double lam[M];
@@ -599,7 +702,7 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
         dxp = 0;
         return;
     }
-    tau = neglog_u_open / s;
+    tau = waiting_time(neglog_u_open, s);
     const double t = u_sel_v * s;
     // With at most two species and four reactions every eta_j fits 16 bits
     // of one 64-bit scalar: J is found by counting and eta_J by a shift.
@@ -628,9 +731,11 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
     if (pj < 0) {  // only for non-finite a0: the last channel with lambda > 0
         uint32_t pos = 0;
         double lam[M];
-        if (kNarrowK) {
+        if constexpr (kNarrowK) {
 #pragma unroll
             for (int j = 0; j < M; ++j) lam[j] = lam_narrow<NS, M>(h, I, ltab, x, j, inr);
+        } else if constexpr (SPEC >= 0) {
+            lams_desc<NS, M, SPEC>(h, I, ltab, x, lam);
         } else {
             lams_general<NS, M>(h, I, ltab, x, lam);
         }
@@ -644,14 +749,22 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
     dxp = d;
 }
 
-template <int NS, int M>
+template <int NS, int M, long long SPEC = -1>
 __device__ __forceinline__ void ssa_event(const HotNet<M>& h, const DevInst* __restrict__ I,
                                           const double* __restrict__ ltab,
                                           const double* __restrict__ lgt, const int (&x)[NS],
                                           const Blk& b, double& tau, int& J, uint32_t& dxp,
                                           double* a0_out = nullptr) {
-    event_from_uniforms<NS, M>(h, I, ltab, x, neglog_u_open(b, lgt), u_sel(b), tau, J, dxp,
+    event_from_uniforms<NS, M, SPEC>(h, I, ltab, x, neglog_u_open(b, lgt), u_sel(b), tau, J, dxp,
                                a0_out);
+}
+
+// The two uniforms of one Gillespie step: -log(u_open) and u_sel.
+struct Uni {
+    double nl, us;
+};
+__device__ __forceinline__ Uni uniforms(const Blk& b, const double* __restrict__ lgt) {
+    return Uni{neglog_u_open(b, lgt), u_sel(b)};
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int j) {
@@ -677,16 +790,44 @@ __device__ __forceinline__ int region_of(const DevInst* __restrict__ I, const in
     return d >= I->region_theta ? 1 : 0;
 }
 
+// Buffers reached through the instance descriptor's pointers are device
+// (global) memory.  Saying so with address space 1 makes the compiler issue
+// global_* instead of flat_* instructions: a flat access also counts against
+// the LDS counter, so every later LDS wait (each barrier of a round) would
+// wait for the HBM round trip of the round's histogram atomics.
+template <class T>
+using gptr_t = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr_t<T> gmem(T* p) {
+    return (gptr_t<T>)p;
+}
+// Relaxed device-scope atomic adds and compare-and-swap in global memory
+// (no return value needed for the adds).
+__device__ __forceinline__ void gadd(double* p, double v) {
+    __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gadd(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long gcas(unsigned long long* p, unsigned long long expect,
+                                                   unsigned long long v) {
+    __hip_atomic_compare_exchange_strong(gmem(p), &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return expect;
+}
+
 template <int NS>
 __device__ __forceinline__ int64_t hist_index(const DevInst* __restrict__ I, const int (&x)[NS]) {
+    // branch-free, so that the box's parameters load together (one wait)
     int64_t idx = 0;
+    bool in = true;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
         const int64_t o = (int64_t)x[i] - I->hist_lo[i];
-        if (o < 0 || o >= I->hist_nb[i]) return -1;
+        in = in & ((uint64_t)o < (uint64_t)(int64_t)I->hist_nb[i]);
         idx += o * I->hist_stride[i];
     }
-    return idx;
+    return in ? idx : -1;
 }
 
 // Time at a state outside the histogram box: totals plus a slot of the
@@ -695,8 +836,8 @@ __device__ __forceinline__ int64_t hist_index(const DevInst* __restrict__ I, con
 template <int NS>
 __device__ __forceinline__ void spill_credit(const DevInst* __restrict__ I, const int (&x)[NS], double full,
                              double w) {
-    atomicAdd(&I->acc[kAccOutside], full);
-    if (w > 0.0) atomicAdd(&I->acc[kAccOutsideW], w);
+    gadd(&I->acc[kAccOutside], full);
+    if (w > 0.0) gadd(&I->acc[kAccOutsideW], w);
     unsigned long long key = 1ull << 63;
     bool ok = true;
 #pragma unroll
@@ -708,15 +849,15 @@ __device__ __forceinline__ void spill_credit(const DevInst* __restrict__ I, cons
         uint32_t h = (uint32_t)(key ^ (key >> 29)) * 0x9E3779B1u;
         for (int probe = 0; probe < kSpillCap; ++probe) {
             SpillSlot* sl = &I->spill[(h + probe) & (kSpillCap - 1)];
-            const unsigned long long old = atomicCAS(&sl->key, 0ull, key);
+            const unsigned long long old = gcas(&sl->key, 0ull, key);
             if (old == 0ull || old == key) {
-                atomicAdd(&sl->full, full);
-                if (w > 0.0) atomicAdd(&sl->w, w);
+                gadd(&sl->full, full);
+                if (w > 0.0) gadd(&sl->w, w);
                 return;
             }
         }
     }
-    atomicAdd((unsigned long long*)&I->counters[PARREP_CNT_SPILL_OVERFLOW], 1ull);
+    gadd((unsigned long long*)&I->counters[PARREP_CNT_SPILL_OVERFLOW], 1ull);
 }
 
 // Credit `full` time at x over [0,T] and `w` of it inside [t_burn, T].
@@ -729,11 +870,11 @@ __device__ __forceinline__ void add_credit(const DevInst* __restrict__ I, const 
         // holds only the time before t_burn: one atomic per credit except
         // for the interval that straddles t_burn (w <= full always).
         if (w > 0.0) {
-            atomicAdd(&I->hist_w[idx], w);
+            gadd(&I->hist_w[idx], w);
             const double pre = full - w;
-            if (pre > 0.0) atomicAdd(&I->hist[idx], pre);
+            if (pre > 0.0) gadd(&I->hist[idx], pre);
         } else {
-            atomicAdd(&I->hist[idx], full);
+            gadd(&I->hist[idx], full);
         }
     } else {
         spill_credit<NS>(I, x, full, w);
@@ -798,7 +939,7 @@ __device__ __attribute__((noinline)) void flush_tile(const DevInst* __restrict__
         const double v = tile[i];
         if (v != 0.0) {
             const int d0 = i / t.n1, d1 = i - d0 * t.n1;
-            atomicAdd(&tgt[base + d0 * s0 + d1 * s1], v);
+            gadd(&tgt[base + d0 * s0 + d1 * s1], v);
             tile[i] = 0.0;
         }
     }
@@ -865,7 +1006,7 @@ template <int E, int WAVES>
 struct Shared {
     int32_t flags[2][WAVES];
     int32_t wmin[2][WAVES];
-    uint64_t wsum[2][WAVES][2];
+    uint64_t wsum[2][WAVES][3];
     uint64_t mask[2][E];
     int32_t cnt[2][E];
     int32_t bi[16];
@@ -901,34 +1042,88 @@ __device__ __forceinline__ int select_bit(uint64_t m, int k) {
     return pos;
 }
 
+// Wave-wide reduction by DPP (data moved between lanes by the VALU, no
+// LDS round trip): xor 1 and xor 2 within quads, the mirror within 8 and
+// within 16 lanes (every lane of a row then holds the row's value), lane 15
+// of rows 0 and 2 into rows 1 and 3, lane 31 into rows 2 and 3; lane 63
+// ends with the whole wave's.  Lanes of rows a step leaves out combine with
+// the identity.  Every lane of the wave must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t identity, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+    return ((uint64_t)dpp32<CTRL, ROWS>(0u, (uint32_t)(v >> 32)) << 32) |
+           dpp32<CTRL, ROWS>(0u, (uint32_t)v);
+}
+
+// A minimum and an exact sum of 64.64 times in three parts that cannot
+// overflow over 1024 lanes: the high words (each at most 2^52) and the two
+// 32-bit halves of the low words.
+struct MinSum3 {
+    int m;
+    uint64_t a, b, c;
+};
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void min_sum_step(MinSum3& r) {
+    r.m = min(r.m, (int)dpp32<CTRL, ROWS>((uint32_t)INT_MAX, (uint32_t)r.m));
+    r.a += dpp64<CTRL, ROWS>(r.a);
+    r.b += dpp64<CTRL, ROWS>(r.b);
+    r.c += dpp64<CTRL, ROWS>(r.c);
+}
+
+__device__ __forceinline__ MinSum3 wave_min_sum(int vmin, Fx v) {
+    MinSum3 r{vmin, v.hi, v.lo >> 32, v.lo & 0xFFFFFFFFull};
+    min_sum_step<0xB1, 0xF>(r);   // quad_perm [1,0,3,2]
+    min_sum_step<0x4E, 0xF>(r);   // quad_perm [2,3,0,1]
+    min_sum_step<0x141, 0xF>(r);  // row_half_mirror
+    min_sum_step<0x140, 0xF>(r);  // row_mirror
+    min_sum_step<0x142, 0xA>(r);  // row_bcast:15
+    min_sum_step<0x143, 0xC>(r);  // row_bcast:31
+    return r;
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Workgroup-wide minimum of vmin and clamped exact sum of vsum (every lane
+// of the workgroup takes part; one barrier).
 template <int E, int WAVES>
 __device__ __forceinline__ void block_min_sum(Shared<E, WAVES>& sh, int& par, int wid, int lane,
                                               int vmin, Fx vsum, int& omin, Fx& osum) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        vmin = min(vmin, __shfl_xor(vmin, off));
-        vsum = fx_add_sat(vsum, shfl_xor_fx(vsum, off));
-    }
+    const MinSum3 r = wave_min_sum(vmin, vsum);
+    const int wm = __builtin_amdgcn_readlane(r.m, 63);
+    const uint64_t wa = readlane_u64(r.a, 63), wb = readlane_u64(r.b, 63),
+                   wc = readlane_u64(r.c, 63);
     if (WAVES == 1) {
-        omin = vmin;
-        osum = vsum;
+        omin = wm;
+        osum = fx_join3(wa, wb, wc);
         return;
     }
     const int p = par;
     par ^= 1;
     if (lane == 0) {
-        sh.wmin[p][wid] = vmin;
-        sh.wsum[p][wid][0] = vsum.hi;
-        sh.wsum[p][wid][1] = vsum.lo;
+        sh.wmin[p][wid] = wm;
+        sh.wsum[p][wid][0] = wa;
+        sh.wsum[p][wid][1] = wb;
+        sh.wsum[p][wid][2] = wc;
     }
     __syncthreads();
     omin = INT_MAX;
-    osum = Fx{0, 0};
+    uint64_t a = 0, b = 0, c = 0;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
         omin = min(omin, sh.wmin[p][w]);
-        osum = fx_add_sat(osum, Fx{sh.wsum[p][w][0], sh.wsum[p][w][1]});
+        a += sh.wsum[p][w][0];
+        b += sh.wsum[p][w][1];
+        c += sh.wsum[p][w][2];
     }
+    osum = fx_join3(a, b, c);
 }
 
 template <int NS>
@@ -983,7 +1178,7 @@ __device__ __forceinline__ Fx readlane_fx(Fx v, int j) {
     return Fx{((uint64_t)a << 32) | b, ((uint64_t)c << 32) | d};
 }
 
-template <int NS, int M>
+template <int NS, int M, long long SPEC = -1>
 __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* __restrict__ I,
                                             const double* __restrict__ ltab,
                                             const double* __restrict__ lgt, RunState& rs, Fx Tq,
@@ -1029,7 +1224,7 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
             double a0, tau_unused;
             int J;
             uint32_t dxp;
-            event_from_uniforms<NS, M>(h, I, ltab, x, 0.0, readlane_f64(us_l, j), tau_unused, J,
+            event_from_uniforms<NS, M, SPEC>(h, I, ltab, x, 0.0, readlane_f64(us_l, j), tau_unused, J,
                                        dxp, &a0);
             const bool me = lane == j;
             a0_l = me ? a0 : a0_l;
@@ -1054,7 +1249,7 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
 
         // Waiting times and the exact clock before / after each event.
         const bool act = lane < nb;
-        const double tau_l = act ? (a0_l > 0.0 ? nl_l / a0_l : __builtin_inf()) : 0.0;
+        const double tau_l = act ? (a0_l > 0.0 ? waiting_time(nl_l, a0_l) : __builtin_inf()) : 0.0;
         const Fx fx_l = act ? fx_from(tau_l) : Fx{0, 0};
         Fx inc = fx_l;
 #pragma unroll
@@ -1132,12 +1327,21 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
 template <int RPL>
 constexpr int kMinWavesPerEU = RPL == 4 ? 5 : 1;
 
-template <int NS, int M, int RPL, int WAVES>
+// SPEC >= 0: a compiled specialisation.  Narrow kernels: one species map
+// (bit j: the species that reaction j's table is read at), with rows at a
+// fixed stride.  General kernels: one network descriptor (desc_pack).
+template <int NS, int M, int RPL, int WAVES, long long SPEC = -1>
 __global__ void __launch_bounds__(64 * WAVES)
 __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL>, 8)))
 k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
            int64_t hook_max_rounds, int tab_lds) {
     constexpr int B = 64 * WAVES;
+    // With one replica per lane a dephasing or parallel round is one
+    // dependent chain per wave, so little hides its latency.  The uniforms
+    // come from counter-based draws that do not depend on the state: each
+    // round takes the next round's a round ahead (Philox and -log(u) then
+    // overlap the event), the same numbers as drawn in place.
+    constexpr bool kAhead = RPL == 1;
     constexpr int E = RPL * WAVES;
     // Loops over a lane's replica slots are unrolled up to 16 slots (the
     // per-slot state stays in registers); with 64 slots they stay rolled and
@@ -1163,7 +1367,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
     // Propensity tables, copied into LDS after the exchange buffer (the
     // launcher reserved tab_lds doubles for them).
     double* ltab = reinterpret_cast<double*>(dyn_lds + ((kXbufInts + 1) & ~1));
-    const TabLayout<M> tl = tab_layout<M, narrow_kernel(NS, M)>(I, tab_lds);
+    const TabLayout<M> tl = tab_layout<M, narrow_kernel(NS, M), SPEC>(I, tab_lds);
     stage_tables<M, narrow_kernel(NS, M)>(I, tl, ltab, tid, B);
     __shared__ double lgt[kLogTabLen];
     for (int i = tid; i < kLogTabLen; i += B) lgt[i] = I->logtab[i];
@@ -1212,7 +1416,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 // other waves wait; raise its issue priority over the waves of
                 // other workgroups sharing the SIMD.
                 __builtin_amdgcn_s_setprio(3);
-                decorrelate<NS, M>(hn, I, ltab, lgt, rs, Fx{rs.Tq_hi, rs.Tq_lo},
+                decorrelate<NS, M, SPEC>(hn, I, ltab, lgt, rs, Fx{rs.Tq_hi, rs.Tq_lo},
                                    Fx{rs.tbq_hi, rs.tbq_lo}, max_ev, key0, key1, lane);
                 __builtin_amdgcn_s_setprio(0);
                 if (lane == 0) {
@@ -1256,6 +1460,10 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             const int64_t n_p = (int64_t)I->dephase;
             const double t_p = I->dephase;
             const int64_t left2 = (max_ev - rs.ev_total) / R;
+            // round 0's uniforms (one replica per lane: see kAhead)
+            Uni ahead{0.0, 0.0};
+            if (kAhead && tid < R)
+                ahead = uniforms(draw(0, (uint32_t)tid, cycle, kTagDephase, key0, key1), lgt);
             const int64_t budget_rounds = (int64_t)ufl64((uint64_t)(left2 > 0 ? left2 : 0));
             bool done = steps ? (n_p <= 0) : (0.0 >= t_p);
             bool budget = false;
@@ -1272,12 +1480,22 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
                     if (r < R) {
-                        const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagDephase, key0,
-                                           key1);
+                        Uni u;
+                        if constexpr (kAhead) {
+                            u = ahead;
+                            ahead = uniforms(draw((uint64_t)round2 + 1, (uint32_t)r, cycle,
+                                                  kTagDephase, key0, key1),
+                                             lgt);
+                        } else {
+                            u = uniforms(draw((uint64_t)round2, (uint32_t)r, cycle, kTagDephase,
+                                              key0, key1),
+                                         lgt);
+                        }
                         double tau;
                         int J;
                         uint32_t dxp;
-                        ssa_event<NS, M>(hn, I, ltab, lgt, Y[k], b, tau, J, dxp);
+                        event_from_uniforms<NS, M, SPEC>(hn, I, ltab, Y[k], u.nl, u.us, tau, J,
+                                                         dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
                         if (region_hot<NS, M>(hn, Y[k]) != W) exitbits |= (SlotMask)1 << k;
@@ -1410,6 +1628,9 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         const Fx Tq = ufx(Fx{rs.Tq_hi, rs.Tq_lo});
         const Fx tbq = ufx(Fx{rs.tbq_hi, rs.tbq_lo});
         int64_t round3 = 0, cred = 0, disc = 0;
+        Uni ahead{0.0, 0.0};
+        if (kAhead && tid < R)
+            ahead = uniforms(draw(0, (uint32_t)tid, cycle, kTagParallel, key0, key1), lgt);
         int outcome = -1;  // 1 exit, 0 horizon, -1 budget
         int Kx = 0;
         double tauk[RPL];
@@ -1444,10 +1665,20 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                 tauk[k] = 0.0;
                 dxk[k] = 0;
                 if (r < R) {
-                    const Blk b = draw((uint64_t)round3, (uint32_t)r, cycle, kTagParallel, key0,
-                                       key1);
+                    Uni u;
+                    if constexpr (kAhead) {
+                        u = ahead;
+                        ahead = uniforms(draw((uint64_t)round3 + 1, (uint32_t)r, cycle,
+                                              kTagParallel, key0, key1),
+                                         lgt);
+                    } else {
+                        u = uniforms(draw((uint64_t)round3, (uint32_t)r, cycle, kTagParallel,
+                                          key0, key1),
+                                     lgt);
+                    }
                     int J;
-                    ssa_event<NS, M>(hn, I, ltab, lgt, Y[k], b, tauk[k], J, dxk[k]);
+                    event_from_uniforms<NS, M, SPEC>(hn, I, ltab, Y[k], u.nl, u.us, tauk[k], J,
+                                                     dxk[k]);
                     int post[NS];
 #pragma unroll
                     for (int i = 0; i < NS; ++i) post[i] = Y[k][i];

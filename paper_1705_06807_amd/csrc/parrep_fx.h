@@ -41,6 +41,19 @@ PARREP_HD inline Fx fx_add_sat(Fx a, Fx b) {
     return r.hi >= kFxSatHi ? Fx{kFxSatHi, 0} : r;
 }
 
+// A sum of times split in three parts that do not overflow over 1024
+// terms: a = the sum of the high words (each at most 2^52), b and c = the
+// sums of the high and low 32-bit halves of the low words.  Returns the
+// 64.64 value a + b 2^-32 + c 2^-64 clamped as fx_add_sat clamps: for
+// non-negative terms the clamp of the exact total equals the clamped sum
+// taken in any order.
+PARREP_HD inline Fx fx_join3(uint64_t a, uint64_t b, uint64_t c) {
+    const uint64_t lb = b << 32;
+    const uint64_t lo = lb + c;
+    const uint64_t hi = a + (b >> 32) + (lo < lb ? 1u : 0u);
+    return hi >= kFxSatHi ? Fx{kFxSatHi, 0} : Fx{hi, lo};
+}
+
 PARREP_HD inline Fx fx_sub(Fx a, Fx b) {
     Fx r;
     r.lo = a.lo - b.lo;

@@ -20,11 +20,26 @@ namespace {
 // the histogram tile when the group's instances stage it.
 template <int NS, int M, int RPL, int WAVES>
 hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64_t hmr,
-                           int tab_lds, int stage, hipStream_t st) {
+                           int tab_lds, int stage, long long spec, hipStream_t st) {
     // the exchange buffer, the tables, and the histogram tile of instances
     // that stage it
     const size_t lead = (xbuf_lds_bytes(RPL, WAVES, NS) / 4 + 1) / 2 * 8;
     const size_t lds = lead + (size_t)tab_lds * 8 + (stage ? (size_t)kTileDoubles * 8 : 0);
+    if constexpr (NS == 2 && M == 4) {
+        if (spec == kMapCross) {
+            hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES, kMapCross>), dim3(n),
+                               dim3(64 * WAVES), lds, st, d, mode, hc, hmr, tab_lds);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (NS == 4 && M == 8 && RPL <= 4) {
+        if (spec == kDescSwitch) {
+            hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES, kDescSwitch>), dim3(n),
+                               dim3(64 * WAVES), lds, st, d, mode, hc, hmr, tab_lds);
+            return hipGetLastError();
+        }
+    }
+    if (spec >= 0) return hipErrorInvalidValue;  // no such specialisation compiled
     hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES>), dim3(n), dim3(64 * WAVES), lds, st, d,
                        mode, hc, hmr, tab_lds);
     return hipGetLastError();
@@ -38,27 +53,27 @@ hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64
 #define PARREP_FN PARREP_CAT(launch_instance_ns, PARREP_NS, _w, PARREP_WAVES)
 
 hipError_t PARREP_FN(const DevInst* d, int n, int m, int rpl, int mode, uint32_t hc, int64_t hmr,
-                     int tab_lds, int stage, hipStream_t st) {
+                     int tab_lds, int stage, long long spec, hipStream_t st) {
     constexpr int NS = PARREP_NS, WV = PARREP_WAVES;
     if (m <= 4) {
         switch (rpl) {
-            case 1: return dev::launch_instance<NS, 4, 1, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
-            case 4: return dev::launch_instance<NS, 4, 4, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
-            case 16: return dev::launch_instance<NS, 4, 16, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
+            case 1: return dev::launch_instance<NS, 4, 1, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
+            case 4: return dev::launch_instance<NS, 4, 4, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
+            case 16: return dev::launch_instance<NS, 4, 16, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
             case 64:
                 if constexpr (WV == 16)
-                    return dev::launch_instance<NS, 4, 64, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
+                    return dev::launch_instance<NS, 4, 64, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
                 return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }
     switch (rpl) {
-        case 1: return dev::launch_instance<NS, 8, 1, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
-        case 4: return dev::launch_instance<NS, 8, 4, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
-        case 16: return dev::launch_instance<NS, 8, 16, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
+        case 1: return dev::launch_instance<NS, 8, 1, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
+        case 4: return dev::launch_instance<NS, 8, 4, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
+        case 16: return dev::launch_instance<NS, 8, 16, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
         case 64:
             if constexpr (WV == 16)
-                return dev::launch_instance<NS, 8, 64, WV>(d, n, mode, hc, hmr, tab_lds, stage, st);
+                return dev::launch_instance<NS, 8, 64, WV>(d, n, mode, hc, hmr, tab_lds, stage, spec, st);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }

@@ -47,6 +47,12 @@ struct SpillSlot {
 constexpr int kSpillCap = 2048;
 // Bins of the LDS histogram tile of the instance kernel (8 KiB).
 constexpr int kTileDoubles = 1024;
+// Row stride (states) of the propensity tables in the narrow kernels compiled
+// for one species map, and the maps compiled: two species with reactions 1
+// and 4 read at species 1 and reactions 2 and 3 at species 0 (the toggle
+// switch's cross-regulated births and linear deaths).
+constexpr int kMapStride = 512;
+constexpr int kMapCross = 0b1001;
 
 // Exchange area of one instance spread over several workgroups (the wide
 // instance kernel): a grid barrier, the chunk results the workgroups agree
@@ -158,11 +164,40 @@ __host__ __device__ constexpr uint32_t jmeta_pack(uint32_t kind, uint32_t sp, ui
 }
 __host__ __device__ constexpr bool narrow_kernel(int ns, int m) { return ns <= 2 && m <= 4; }
 
+// Compiled network descriptors of the general kernels: the jmeta of
+// reactions 0..5 in bits 10j..10j+9 and the reaction count in bits 60..62.
+// With every reaction's kind, species and tail fixed at compile time the
+// propensities index the state by constants, so no runtime selection (and
+// no indexed private array) sits in the event chain; rate constants, tables
+// and stoichiometry stay runtime data.
+constexpr int kDescMaxM = 6;
+__host__ __device__ constexpr long long desc_pack(const uint32_t (&meta)[kDescMaxM], int m) {
+    long long d = (long long)m << 60;
+    for (int j = 0; j < kDescMaxM && j < m; ++j) d |= (long long)(meta[j] & 0x3FFu) << (10 * j);
+    return d;
+}
+__host__ __device__ constexpr int desc_count(long long d) { return (int)((d >> 60) & 7); }
+__host__ __device__ constexpr uint32_t desc_meta(long long d, int j) {
+    return j < desc_count(d) ? (uint32_t)(d >> (10 * j)) & 0x3FFu : jmeta_pack(kRxConst, 0, 0, 0, 0);
+}
+// The genetic switch of Sec. IV B (species DNA_in, DNA_act, mRNA, protein):
+// transcription a x1, mRNA decay gamma x2, translation gamma b x2, protein
+// decay x3 (falling factorials), and the switching reactions F(x3) x0 and
+// G(x3) x1 (protein tables with a DNA tail).
+constexpr uint32_t kDescSwitchMeta[kDescMaxM] = {
+    jmeta_pack(kRxFall, 1, 1, 0, 0),  jmeta_pack(kRxFall, 2, 1, 0, 0),
+    jmeta_pack(kRxFall, 2, 1, 0, 0),  jmeta_pack(kRxFall, 3, 1, 0, 0),
+    jmeta_pack(kRxTable, 3, 0, 0, 1), jmeta_pack(kRxTable, 3, 0, 1, 1)};
+constexpr long long kDescSwitch = desc_pack(kDescSwitchMeta, 6);
+
 struct LaunchShape {
     int rpl, waves, ns;
     int m;                 // reactions (the kernel is specialised for m <= 4 and m <= 8)
     int wide = 0;          // > 0: one instance over this many workgroups (4 waves each)
     int stage_flush = -1;  // histogram staging of the group's instances (DevInst::stage_flush)
+    // compiled specialisation every instance of the group fits (-1: none):
+    // a species map (narrow kernels) or a network descriptor (general kernels)
+    long long spec = -1;
 };
 
 // Launchers (parrep_kernels.hip).
@@ -174,6 +209,16 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape shape, in
 // (the kernel shortens the longest tables to fit; states beyond take the
 // formula).
 int table_lds_need(const DevInst& d, LaunchShape shape);
+// The compiled species map (kMapCross) an instance of this shape can run
+// with, or -1: two species, four reactions, every reaction a table or a
+// constant, tables indexed as the map says, and the table within the map's
+// row stride.
+int species_map(const DevInst& d, LaunchShape shape);
+// The compiled network descriptor (kDescSwitch) an instance of this shape
+// can run with, or -1: a 4-species general kernel with at most 4 replicas
+// per lane (not spread over workgroups) whose reactions' hot meta equals the
+// descriptor's.
+long long network_desc(const DevInst& d, LaunchShape shape);
 int table_lds_doubles(LaunchShape shape, int max_need);
 hipError_t launch_zero(const DevInst* d_inst, int n_inst, hipStream_t stream);
 // One instance over s.wide workgroups (cooperative launch; s.rpl 1 or 4).

@@ -427,7 +427,7 @@ LaunchShape choose_shape(int R, int ns, int m) {
 
 #define PARREP_DECL(NSv, Wv)                                                                  \
     hipError_t launch_instance_ns##NSv##_w##Wv(const DevInst*, int, int, int, int, uint32_t,     \
-                                               int64_t, int, int, hipStream_t);
+                                               int64_t, int, int, long long, hipStream_t);
 PARREP_DECL(1, 1) PARREP_DECL(1, 4) PARREP_DECL(1, 16)
 PARREP_DECL(2, 1) PARREP_DECL(2, 4) PARREP_DECL(2, 16)
 PARREP_DECL(4, 1) PARREP_DECL(4, 4) PARREP_DECL(4, 16)
@@ -441,7 +441,7 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mo
     if (s.ns == NSv && s.waves == Wv)                                                         \
         return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.m, s.rpl, mode, hook_cycle,  \
                                                hook_max_rounds, tab_lds, s.stage_flush >= 0,   \
-                                               stream);
+                                               s.spec, stream);
     PARREP_GO(1, 1) PARREP_GO(1, 4) PARREP_GO(1, 16)
     PARREP_GO(2, 1) PARREP_GO(2, 4) PARREP_GO(2, 16)
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)
@@ -471,8 +471,31 @@ hipError_t launch_setup(DevInst* d_inst, int n_inst, hipStream_t stream) {
     return hipGetLastError();
 }
 
+int species_map(const DevInst& d, LaunchShape s) {
+    if (s.wide || s.ns != 2 || s.m > 4 || d.net.n_species != 2 || d.tab_L > kMapStride) return -1;
+    for (int j = 0; j < d.net.n_reactions; ++j) {
+        const uint32_t kind = d.jmeta[j] & 3u;
+        if (kind == kRxConst) continue;  // a constant row reads the same at any state
+        if (kind != kRxTable) return -1;
+        if ((int)((d.jmeta[j] >> 2) & 3u) != ((kMapCross >> j) & 1)) return -1;
+    }
+    return kMapCross;
+}
+
+long long network_desc(const DevInst& d, LaunchShape s) {
+    // compiled for 4 species, up to 8 reactions and 1 or 4 replicas per lane
+    if (s.wide || s.ns != 4 || s.m > 8 || s.rpl > 4 || d.net.n_species > 4 ||
+        d.net.n_reactions > kDescMaxM)
+        return -1;
+    uint32_t meta[kDescMaxM] = {};
+    for (int j = 0; j < d.net.n_reactions; ++j) meta[j] = d.jmeta[j];
+    const long long mine = desc_pack(meta, d.net.n_reactions);
+    return mine == kDescSwitch ? kDescSwitch : -1;
+}
+
 int table_lds_need(const DevInst& d, LaunchShape s) {
     const int M = s.m <= 4 ? 4 : 8;
+    if (s.spec >= 0 && narrow_kernel(s.ns, s.m)) return M * kMapStride;
     if (narrow_kernel(s.ns, s.m)) return M * d.tab_L;
     int need = 0;
     for (int j = 0; j < d.net.n_reactions; ++j)

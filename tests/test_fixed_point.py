@@ -7,7 +7,10 @@ and the burn-in time are crossed at one event whatever the summation order).
   rational arithmetic;
 * the replica sums saturate: 4096 absorbing replicas (4096 x 2^52 = 2^64)
   wrap the plain 64-bit high word to 0, which would hide the horizon from
-  the parallel step; the saturating sum equals min(exact sum, 2^52).
+  the parallel step; the saturating sum equals min(exact sum, 2^52);
+* the workgroup reductions' three-part sums (high words, and the two halves
+  of the low words, summed over up to 1024 lanes in any order) joined by
+  fx_join3 equal the saturating sum, with and without saturation.
 """
 import math
 import os
@@ -34,9 +37,11 @@ def fx(tmp_path_factory):
     def run(ds):
         out = subprocess.run([exe], input="\n".join(float.hex(d) for d in ds) + "\n",
                              capture_output=True, text=True, check=True).stdout.splitlines()
-        vals = [tuple(int(w, 16) for w in line.split()) for line in out[:-2]]
-        plain = tuple(int(w, 16) for w in out[-2].split()[1:])
-        sat = tuple(int(w, 16) for w in out[-1].split()[1:])
+        vals = [tuple(int(w, 16) for w in line.split()) for line in out[:-4]]
+        plain = tuple(int(w, 16) for w in out[-4].split()[1:])
+        sat = tuple(int(w, 16) for w in out[-3].split()[1:])
+        run.join3 = tuple(int(w, 16) for w in out[-2].split()[1:])
+        run.sat1024 = tuple(int(w, 16) for w in out[-1].split()[1:])
         return vals, plain, sat
     return run
 
@@ -82,3 +87,23 @@ def test_finite_sums_are_exact(fx):
     exact = sum(_exact(d) for d in ds)
     assert (plain[0] << 64) | plain[1] == exact
     assert sat == plain
+
+
+@pytest.mark.parametrize("case", ["small", "carries", "saturated", "one_inf", "empty_lo"])
+def test_three_part_join_equals_saturating_sum(fx, case):
+    rng = random.Random(case)
+    if case == "small":
+        ds = [rng.expovariate(300.0) for _ in range(1024)]
+    elif case == "carries":  # low words near 2^64: the halves' sums carry into the high word
+        ds = [1.0 - 2.0 ** -40 * rng.random() for _ in range(1024)]
+    elif case == "saturated":  # 1024 absorbing lanes: 1024 x 2^52 in the high words
+        ds = [math.inf] * 1024
+    elif case == "one_inf":
+        ds = [rng.expovariate(1.0) for _ in range(1023)] + [math.inf]
+        rng.shuffle(ds)
+    else:  # integral times only (low words 0) and one just below saturation
+        ds = [float(rng.randint(0, 1000)) for _ in range(1023)] + [2.0 ** 52 - 2.0 ** 20]
+    fx(ds)
+    exact = sum(_exact(d) for d in ds[:1024])
+    assert (fx.join3[0] << 64) | fx.join3[1] == min(exact, SAT << 64)
+    assert fx.join3 == fx.sat1024

@@ -21,9 +21,10 @@ from paper_1705_06807_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-12
-# tau = -log(u)/a0: the device log is within 0.8 ulp, the C library's within
-# about 0.5, and each side rounds the quotient once: 2.5 ulp in all.
-TAU_RTOL = 2.5 * 2.0 ** -52
+# tau = -log(u)/a0: the device log is within 0.8 ulp and its quotient (-log u
+# times a Newton-refined 1/a0) within 1.5 more; the C library's log is within
+# about 0.5 ulp and its IEEE quotient within 0.5 more: 3.5 ulp in all.
+TAU_RTOL = 3.5 * 2.0 ** -52
 
 
 def _flush(msg):
