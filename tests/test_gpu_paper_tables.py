@@ -221,3 +221,39 @@ def test_genetic_switch_accuracy_vs_thresholds(B):
               flush=True)
     assert dev[5e3][0] < -0.3 * exact
     assert abs(dev[1e5][0]) < 4 * dev[1e5][1]
+
+
+def test_paper_schlogl_accuracy_vs_thresholds(B):
+    """Sec. IV A's sweep over the decorrelation and dephasing thresholds: the
+    stationary mean of x from 100 trajectories per setting (R = 100, T = 1e5,
+    averaged over the window [T/2, T]) against the exact mean 72.4495 of the
+    birth-death law, with the speedup (serial SSA steps over ParRep's on R
+    ideal processors) for each setting.  For n_c = n_p >= 1000 (the settings
+    the paper keeps) the mean agrees with the exact one to four standard
+    errors and the speedup falls as the thresholds grow; the smaller settings
+    are printed for context (the paper drops them as inaccurate)."""
+    import torch
+    N, T = 100, 1e5
+    exact = float(np.dot(E.schlogl_paper_pi(400), np.arange(401)))
+    ns = (10, 30, 100, 300, 1000, 2000, 3000, 4000, 5000)
+    probs = [W.paper_schlogl_problem(seed=21, instance_id=j * N + i, T=T, n_c=n, n_p=n)
+             for j, n in enumerate(ns) for i in range(N)]
+    print("Schloegl threshold sweep: %d settings x %d trajectories, T=%g, R=100"
+          % (len(ns), N, T), flush=True)
+    outs = B.parrep_solve_batch(probs, cycle_log_cap=0)
+    torch.cuda.synchronize()
+    hs = [o.to_host() for o in outs]
+    assert [h.T_s for h in hs] == [T] * len(probs)
+    res = {}
+    for j, n in enumerate(ns):
+        part = hs[j * N:(j + 1) * N]
+        y = np.array([h.y[0] for h in part]) / (T / 2)
+        se = y.std(ddof=1) / math.sqrt(N)
+        c = np.array([o.counters.cpu().numpy() for o in outs[j * N:(j + 1) * N]]).sum(axis=0)
+        sp = (c[0] + c[2]) / (c[0] + c[6] + c[5])
+        res[n] = (y.mean(), se, sp)
+        print("n_c = n_p = %5d: mean %.3f +- %.3f (95%%), rel. error %+.3f%%, speedup %.1f"
+              % (n, y.mean(), 1.96 * se, 100 * (y.mean() / exact - 1), sp), flush=True)
+    for n in (1000, 2000, 3000, 4000, 5000):
+        assert abs(res[n][0] - exact) < 4 * res[n][1], (n, res[n], exact)
+    assert res[1000][2] > res[3000][2] > res[5000][2]
