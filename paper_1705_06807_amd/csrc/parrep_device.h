@@ -881,6 +881,18 @@ __device__ __forceinline__ void add_credit(const DevInst* __restrict__ I, const 
     }
 }
 
+// Credit tau at x wholly on one side of t_burn: to hist_w after it (win),
+// to hist before it.  A non-boundary parallel round lies on one side for the
+// whole workgroup, so the side is a uniform branch.  Same sums as
+// add_credit(x, tau, win ? tau : 0) (a zero tau adds +0 to either).
+template <int NS>
+__device__ __forceinline__ void credit_side(const DevInst* __restrict__ I, const int (&x)[NS],
+                                            double tau, bool win) {
+    const int64_t idx = hist_index<NS>(I, x);
+    if (idx >= 0) gadd(&(win ? I->hist_w : I->hist)[idx], tau);
+    else spill_credit<NS>(I, x, tau, win ? tau : 0.0);
+}
+
 // The generic crediting rule for one holding interval [C, C + tau) at x,
 // truncated at the horizon; returns true when the horizon is reached.
 template <int NS>
@@ -1727,7 +1739,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                             if (r < K) {
                                 const int ts = tile_slot<NS>(tw, Y[k]);
                                 if (ts >= 0) atomicAdd(&tile[ts], tauk[k]);
-                                else add_credit<NS>(I, Y[k], tauk[k], win ? tauk[k] : 0.0);
+                                else credit_side<NS>(I, Y[k], tauk[k], win);
                             }
                         }
                         ++since;
@@ -1735,7 +1747,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
 #pragma unroll kUK
                         for (int k = 0; k < RPL; ++k) {
                             const int r = k * B + tid;
-                            if (r < K) add_credit<NS>(I, Y[k], tauk[k], win ? tauk[k] : 0.0);
+                            if (r < K) credit_side<NS>(I, Y[k], tauk[k], win);
                         }
                     }
                 }

@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_wide(const DevInst* __restrict__
                         int J;
                         uint32_t dxp;
                         ssa_event<NS, M>(hn, I, ltab, lgt, Y[k], b, tau, J, dxp);
-                        add_credit<NS>(I, Y[k], tau, win ? tau : 0.0);
+                        credit_side<NS>(I, Y[k], tau, win);
                         apply_dx<NS>(Y[k], dxp);
                     }
                 }
