@@ -1023,6 +1023,7 @@ struct Shared {
     int32_t cnt[2][E];
     int32_t bi[16];
     uint64_t bu[8];
+    int64_t e2[2][WAVES];  // chunked dephasing: each wave's first exit round
 };
 
 __device__ __forceinline__ Fx shfl_xor_fx(Fx v, int off) {
@@ -1354,6 +1355,8 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
     // round takes the next round's a round ahead (Philox and -log(u) then
     // overlap the event), the same numbers as drawn in place.
     constexpr bool kAhead = RPL == 1;
+    // Chunked dephasing (STEPS mode) for the same shapes, with several waves.
+    constexpr int kChunkS2 = (RPL == 1 && WAVES > 1) ? 32 : 0;
     constexpr int E = RPL * WAVES;
     // Loops over a lane's replica slots are unrolled up to 16 slots (the
     // per-slot state stays in registers); with 64 slots they stay rolled and
@@ -1480,14 +1483,10 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             bool done = steps ? (n_p <= 0) : (0.0 >= t_p);
             bool budget = false;
             int64_t fv = 0;
-            while (!done) {
-                if (round2 >= budget_rounds) {
-                    budget = true;
-                    break;
-                }
-                const int p = (int)(round2 & 1);
+            // One dephasing round n of this thread's replicas: the slots whose
+            // replica left W; nd is set when one is still short of t_p.
+            auto dephase_round = [&](int64_t n, bool& nd) -> SlotMask {
                 SlotMask exitbits = 0;
-                bool nd = false;
 #pragma unroll kUK
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
@@ -1495,11 +1494,11 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         Uni u;
                         if constexpr (kAhead) {
                             u = ahead;
-                            ahead = uniforms(draw((uint64_t)round2 + 1, (uint32_t)r, cycle,
+                            ahead = uniforms(draw((uint64_t)n + 1, (uint32_t)r, cycle,
                                                   kTagDephase, key0, key1),
                                              lgt);
                         } else {
-                            u = uniforms(draw((uint64_t)round2, (uint32_t)r, cycle, kTagDephase,
+                            u = uniforms(draw((uint64_t)n, (uint32_t)r, cycle, kTagDephase,
                                               key0, key1),
                                          lgt);
                         }
@@ -1514,6 +1513,127 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                         if (!(tr[k] >= t_p)) nd = true;
                     }
                 }
+                return exitbits;
+            };
+            // Exact Fleming-Viot restart after round n, in which some replica
+            // left W (the whole workgroup takes part): survivors keep their
+            // post-round state; each exited replica copies the post-round
+            // state of survivor floor(u |S| / 2^32), in ascending replica
+            // order.  The exchange buffer and masks are single: the next exit
+            // round writes them only after that round's agreement barrier,
+            // which every wave reaches after its reads here.
+            auto fv_restart = [&](int64_t n, SlotMask exitbits) {
+                int32_t* xb = xbuf;
+#pragma unroll kUK
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = k * B + tid;
+                    if (r < R) {
+#pragma unroll
+                        for (int i = 0; i < NS; ++i) xb[r * NS + i] = Y[k][i];
+                    }
+                    const bool surv = (r < R) && !((exitbits >> k) & 1);
+                    const uint64_t m = __ballot(surv);
+                    if (lane == 0) {
+                        sh.mask[0][k * WAVES + wid] = m;
+                        sh.cnt[0][k * WAVES + wid] = __popcll(m);
+                    }
+                }
+                __syncthreads();
+                int nS = 0;
+                for (int e = 0; e < E; ++e) nS += sh.cnt[0][e];
+                nS = ufl(nS);
+                if (exitbits) {
+#pragma unroll kUK
+                    for (int k = 0; k < RPL; ++k) {
+                        if (!((exitbits >> k) & 1)) continue;
+                        const int r = k * B + tid;
+                        if (nS > 0) {
+                            const Blk b = draw((uint64_t)n, (uint32_t)r, cycle, kTagFV, key0, key1);
+                            int idx = (int)(((uint64_t)b.w0 * (uint64_t)nS) >> 32);
+                            int e = 0;
+                            for (;;) {
+                                const int c = sh.cnt[0][e];
+                                if (idx < c) break;
+                                idx -= c;
+                                ++e;
+                            }
+                            const int l = select_bit(sh.mask[0][e], idx);
+                            const int rr = (e / WAVES) * B + (e % WAVES) * 64 + l;
+#pragma unroll
+                            for (int i = 0; i < NS; ++i) Y[k][i] = xb[rr * NS + i];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
+                        }
+                    }
+                }
+                fv += R - nS;
+            };
+            // STEPS mode with one replica per lane (a latency-bound shape):
+            // between restarts the waves' replicas are independent and every
+            // round's uniforms come from counters, so each wave runs a chunk
+            // of up to kChunkS2 rounds with no barrier, stopping at its first
+            // round with an exit.  The waves then agree on the first such
+            // round; those that ran past it rewind to the chunk's start and
+            // replay up to it, which leaves every replica where the round-by-
+            // round protocol below would have it.  (The phase's end, n_p
+            // rounds, is known in advance in STEPS mode.)
+            const bool chunked = kChunkS2 && steps;
+            int64_t chunk = 0;
+            while (!done) {
+                if (round2 >= budget_rounds) {
+                    budget = true;
+                    break;
+                }
+                if (chunked) {
+                    const int64_t c0 = round2;
+                    int64_t L = kChunkS2;
+                    L = L < n_p - c0 ? L : n_p - c0;
+                    L = L < budget_rounds - c0 ? L : budget_rounds - c0;
+                    int Y0[RPL][NS];
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k)
+#pragma unroll
+                        for (int i = 0; i < NS; ++i) Y0[k][i] = Y[k][i];
+                    const Uni ahead0 = ahead;
+                    SlotMask exitbits = 0;
+                    int64_t ew = INT64_MAX;
+                    bool nd = false;
+                    for (int64_t n = c0; n < c0 + L; ++n) {
+                        exitbits = dephase_round(n, nd);
+                        if (__ballot(exitbits != 0) != 0ull) {
+                            ew = n;
+                            break;
+                        }
+                    }
+                    const int q = (int)(chunk & 1);
+                    ++chunk;
+                    if (lane == 0) sh.e2[q][wid] = ew;
+                    __syncthreads();
+                    int64_t ef = INT64_MAX;
+#pragma unroll
+                    for (int w = 0; w < WAVES; ++w) ef = ef < sh.e2[q][w] ? ef : sh.e2[q][w];
+                    ef = (int64_t)ufl64((uint64_t)ef);
+                    if (ef == INT64_MAX) {
+                        round2 = c0 + L;
+                    } else {
+                        if (ew != ef) {  // this wave ran past the exit round: replay to it
+#pragma unroll
+                            for (int k = 0; k < RPL; ++k)
+#pragma unroll
+                                for (int i = 0; i < NS; ++i) Y[k][i] = Y0[k][i];
+                            ahead = ahead0;
+                            for (int64_t n = c0; n <= ef; ++n) exitbits = dephase_round(n, nd);
+                        }
+                        fv_restart(ef, exitbits);
+                        round2 = ef + 1;
+                    }
+                    done = round2 >= n_p;
+                    continue;
+                }
+                const int p = (int)(round2 & 1);
+                bool nd = false;
+                const SlotMask exitbits = dephase_round(round2, nd);
                 // One barrier per round: each wave posts whether one of its
                 // replicas left W and whether one is still short of t_p.  The
                 // flags alternate between two slots, so the posts of round
@@ -1526,61 +1646,7 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
 #pragma unroll
                 for (int w = 0; w < WAVES; ++w) fl |= sh.flags[p][w];
                 fl = ufl(fl);
-                if (fl & 2) {
-                    // Some replica left W: exact Fleming-Viot restart.  Survivors
-                    // keep their post-round state; each exited replica copies the
-                    // post-round state of survivor floor(u |S| / 2^32), in
-                    // ascending replica order.  The exchange buffer and masks
-                    // are single: the next exit round writes them only after
-                    // that round's flag barrier, which every wave reaches after
-                    // its reads here.
-                    int32_t* xb = xbuf;
-#pragma unroll kUK
-                    for (int k = 0; k < RPL; ++k) {
-                        const int r = k * B + tid;
-                        if (r < R) {
-#pragma unroll
-                            for (int i = 0; i < NS; ++i) xb[r * NS + i] = Y[k][i];
-                        }
-                        const bool surv = (r < R) && !((exitbits >> k) & 1);
-                        const uint64_t m = __ballot(surv);
-                        if (lane == 0) {
-                            sh.mask[0][k * WAVES + wid] = m;
-                            sh.cnt[0][k * WAVES + wid] = __popcll(m);
-                        }
-                    }
-                    __syncthreads();
-                    int nS = 0;
-                    for (int e = 0; e < E; ++e) nS += sh.cnt[0][e];
-                    nS = ufl(nS);
-                    if (exitbits) {
-#pragma unroll kUK
-                        for (int k = 0; k < RPL; ++k) {
-                            if (!((exitbits >> k) & 1)) continue;
-                            const int r = k * B + tid;
-                            if (nS > 0) {
-                                const Blk b = draw((uint64_t)round2, (uint32_t)r, cycle, kTagFV,
-                                                   key0, key1);
-                                int idx = (int)(((uint64_t)b.w0 * (uint64_t)nS) >> 32);
-                                int e = 0;
-                                for (;;) {
-                                    const int c = sh.cnt[0][e];
-                                    if (idx < c) break;
-                                    idx -= c;
-                                    ++e;
-                                }
-                                const int l = select_bit(sh.mask[0][e], idx);
-                                const int rr = (e / WAVES) * B + (e % WAVES) * 64 + l;
-#pragma unroll
-                                for (int i = 0; i < NS; ++i) Y[k][i] = xb[rr * NS + i];
-                            } else {
-#pragma unroll
-                                for (int i = 0; i < NS; ++i) Y[k][i] = xt[i];
-                            }
-                        }
-                    }
-                    fv += R - nS;
-                }
+                if (fl & 2) fv_restart(round2, exitbits);
                 ++round2;
                 done = steps ? (round2 >= n_p) : ((fl & 1) == 0);
             }
