@@ -221,6 +221,26 @@ def test_launch_shapes_agree(B, oracle, shape):
         assert_same(oracle.run(p, cycle_log_cap=4096), o.to_host(), what=str(shape))
 
 
+@pytest.mark.parametrize("shape,R", [((1, 4), 230), ((1, 16), 700)])
+def test_chunked_dephasing_replays(B, oracle, shape, R):
+    """STEPS-mode dephasing with one replica per lane over several waves runs
+    in barrier-free chunks and rewinds every wave to the first round with an
+    exit (replaying from the chunk start).  Omega = 5 with replicas in every
+    wave (the last one ragged) exits in most rounds, so nearly every chunk
+    replays; the result must still equal the round-by-round oracle."""
+    import torch
+    probs = [_toggle_small(i, R=R, T=40.0, decorr_mode=W.STEPS, decorr=50,
+                           dephase_mode=W.STEPS, dephase=300) for i in range(3)]
+    _flush("chunked dephasing shape %s R=%d" % (shape, R))
+    outs = B.parrep_solve_batch(probs, replicas_per_lane=shape[0], waves=shape[1],
+                                cycle_log_cap=4096)
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        h = o.to_host()
+        assert h.counters["fv_restarts"] > 0
+        assert_same(oracle.run(p, cycle_log_cap=4096), h, what="chunked %s" % (shape,))
+
+
 def test_mixed_batch_equals_oracle(B, oracle):
     import torch
     probs = W.c3_batch(seed=0, n_schlogl=6, n_toggle=6, r_lo=16, r_hi=700, T_schlogl=20.0,
