@@ -696,12 +696,6 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
         }
     }
     if (a0_out) *a0_out = s;
-    if (!(s > 0.0)) {
-        tau = __builtin_inf();
-        J = -1;
-        dxp = 0;
-        return;
-    }
     tau = waiting_time(neglog_u_open, s);
     const double t = u_sel_v * s;
     // With at most two species and four reactions every eta_j fits 16 bits
@@ -716,7 +710,6 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
 #pragma unroll
         for (int j = 0; j < M - 1; ++j) pj += t >= cum[j] ? 1 : 0;
         d = (uint32_t)(h.spack >> (16 * pj)) & 0xFFFFu;
-        if (!(t < cum[M - 1])) pj = -1;  // only for non-finite a0
     } else {
         pj = -1;
         d = 0;
@@ -728,22 +721,32 @@ __device__ __forceinline__ void event_from_uniforms(const HotNet<M>& h,
             }
         }
     }
-    if (pj < 0) {  // only for non-finite a0: the last channel with lambda > 0
-        uint32_t pos = 0;
-        double lam[M];
-        if constexpr (kNarrowK) {
-#pragma unroll
-            for (int j = 0; j < M; ++j) lam[j] = lam_narrow<NS, M>(h, I, ltab, x, j, inr);
-        } else if constexpr (SPEC >= 0) {
-            lams_desc<NS, M, SPEC>(h, I, ltab, x, lam);
+    // Off the common path: no partial sum above t.  For a finite a0 > 0,
+    // t = u_sel a0 < a0 always (u_sel <= 1 - 2^-53), so this is a0 = 0 (an
+    // absorbing state: tau = +inf and no jump; NaN counts as 0) or a0 not
+    // finite (the last channel with lambda > 0).
+    if (__builtin_expect(!(t < cum[M - 1]), 0)) {
+        if (!(s > 0.0)) {
+            tau = __builtin_inf();
+            pj = -1;
+            d = 0;
         } else {
-            lams_general<NS, M>(h, I, ltab, x, lam);
-        }
+            uint32_t pos = 0;
+            double lam[M];
+            if constexpr (kNarrowK) {
 #pragma unroll
-        for (int j = 0; j < M; ++j)
-            if (lam[j] > 0.0) pos |= 1u << j;
-        pj = 31 - __clz(pos);
-        d = I->jstoich[pj];
+                for (int j = 0; j < M; ++j) lam[j] = lam_narrow<NS, M>(h, I, ltab, x, j, inr);
+            } else if constexpr (SPEC >= 0) {
+                lams_desc<NS, M, SPEC>(h, I, ltab, x, lam);
+            } else {
+                lams_general<NS, M>(h, I, ltab, x, lam);
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (lam[j] > 0.0) pos |= 1u << j;
+            pj = 31 - __clz(pos);
+            d = I->jstoich[pj];
+        }
     }
     J = pj;
     dxp = d;
@@ -1509,8 +1512,8 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
                                                          dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
-                        if (region_hot<NS, M>(hn, Y[k]) != W) exitbits |= (SlotMask)1 << k;
-                        if (!(tr[k] >= t_p)) nd = true;
+                        exitbits |= (SlotMask)(region_hot<NS, M>(hn, Y[k]) != W ? 1 : 0) << k;
+                        nd = nd | !(tr[k] >= t_p);
                     }
                 }
                 return exitbits;
