@@ -30,13 +30,13 @@ METRIC = "SSA events/s on 1 GPU (% VALU peak); batched/served ParRep solves/s + 
 # multiply-add is full rate, measured, and the FP64 reciprocal quarter rate,
 # 4 slots): Philox4x32-10 10 rounds x (2 multiply-adds + 2 three-way XORs)
 # = 40; two 53-bit uniforms 10; -log(u) by table reduction and a degree-7
-# log1p 16; four table propensities and their partial sums 9; tau = E/a0
-# correctly rounded (reciprocal, two Newton steps, residual correction) 13;
-# selection 9; jump 4; set test 2; replica clock 2.  Total 105.
-VALU_SLOTS_PER_EVENT = 105
+# log1p 16; four table propensities and their partial sums 9; tau = E/a0 as
+# E times the reciprocal of a0 refined by two Newton steps 6; selection 9;
+# jump 4; set test 2; replica clock 2.  Total 98.
+VALU_SLOTS_PER_EVENT = 98
 # FP64 VALU instructions per event in the built kernel (rocprofv3 counters
 # SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 over events, toggle workload).
-FP64_OPS_PER_EVENT_ISA = 28.44
+FP64_OPS_PER_EVENT_ISA = 26.41
 # MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz, a wave64 VALU op takes 4 cycles
 # -> 256*4*16*2.4e9 = 3.93e13 lane-op slots per second.
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
@@ -48,8 +48,8 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "781b2205f45a1968a5d3867b744c300133ee9995a2afdb4f79379417e6118787",
-           "fetch_kib": 1447148.8125, "write_kib": 5686557758.21875,
+           "sources_sha256": "98edd6d9c4b9179a99d88076e8087460dd4ac830fed31442a325f9db33a08d84",
+           "fetch_kib": 99430139.5, "write_kib": 7887960237.875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
 
@@ -473,11 +473,19 @@ def main():
     if toggle and args.rpl == 0 and args.waves == 0 and args.staging == 0 and not args.no_autotune:
         # untimed: pick the launch shape and histogram staging for R = 1024 on
         # copies with the horizon cut to T/10 (the same mix of steps: every
-        # cycle dephases all replicas, the parallel step credits ~T a0 events)
+        # cycle dephases all replicas, the parallel step credits ~T a0 events).
+        # Up to 16384 copies, each with its own histograms (42 GB here): the
+        # LDS a staging tile takes lowers the workgroups per CU, which a trial
+        # shows only when it fills the device for many waves of workgroups,
+        # and copies that share one histogram contend on its bins as the
+        # batch's trajectories do not.  (1024 copies, or copies sharing one
+        # histogram, picked staging: 2.44e11 events/s at full size against
+        # 2.68e11 without it.)
         t = time.perf_counter()
         shape = B.parrep_autotune(probs[0].replace(instance_id=1 << 30, T=args.T / 10,
                                                    t_burn=args.T / 20),
-                                  instances=1024, trial_events=1 << 40, ctx=ctx)
+                                  instances=min(args.instances, 16384), trial_events=1 << 40,
+                                  ctx=ctx)
         log("autotune: replicas_per_lane=%d waves=%d staging=%d flush=%d (%.1f s)"
             % (shape + (time.perf_counter() - t,)))
     outs = [B.Outputs(ctx, p, cycle_log_cap=0, phase_clock=args.phase_clock) for p in probs]

@@ -206,7 +206,9 @@ typedef struct {
     int32_t chunk_rounds[2];    /* spread runs: dephasing and parallel-step chunk
                                    lengths in rounds (0 = 512 and 64; the second <= 64) */
     int32_t barrier_wait_us;    /* spread runs: longest wait at a meeting point       */
-    int32_t histogram_staging;  /* parallel-step credits (<= 2 species, <= 4 reactions):
+    int32_t histogram_staging;  /* parallel-step credits (<= 2 species, <= 4 reactions,
+                                   <= 4 replicas per lane, <= 4 waves; other shapes
+                                   credit directly):
                                    0 = library choice (the autotuned setting, else off),
                                    -1 = one HBM atomic per credit, 1 = credits at states
                                    in a 1024-bin tile of the box (placed per parallel
@@ -328,8 +330,11 @@ void parrep_plan_destroy(parrep_plan* plan);
  * every histogram staging setting (off, flushed at the step's end, flushed
  * every 64 rounds), keeps the fastest for R's bucket (the next power of two
  * >= max(R, 64)), this species count and reaction class, and returns it in
- * *chosen.  scratch: device buffers that
- * all trial instances overwrite (their values are meaningless).  Blocking. */
+ * *chosen.  scratch: device buffers that all trial instances overwrite
+ * (their values are meaningless), except the histograms: the library
+ * allocates one pair per trial instance (up to 64 GiB in all, freed before it
+ * returns; beyond that the trials share scratch's), so that the trials'
+ * credits do not contend as no real batch's do.  Blocking. */
 int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem* prob,
                     int32_t instances, int64_t trial_events, const parrep_result* scratch,
                     parrep_launch* chosen);

@@ -331,8 +331,10 @@ std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
         groups.back().count += 1;
     }
     for (Group& g : groups) {
-        // staging applies to the narrow kernels only
-        if (!narrow_kernel(g.shape.ns, g.shape.m)) g.shape.stage_flush = -1;
+        // staging applies to the narrow kernels with at most 4 replicas per
+        // lane and at most 4 waves
+        if (!narrow_kernel(g.shape.ns, g.shape.m) || g.shape.rpl > 4 || g.shape.waves > 4)
+            g.shape.stage_flush = -1;
         // a compiled specialisation when every instance of the group fits
         // it: the species-map kernel (its fixed-stride tables must also fit
         // the LDS budget) or the network-descriptor kernel

@@ -233,22 +233,37 @@ int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem
     if (e == hipSuccess) e = hipEventCreate(&eb);
     if (e == hipSuccess) e = hipEventCreate(&ea);
     if (e != hipSuccess) return hip_fail(e, "autotune setup");
+    // Each trial instance credits its own histogram pair, as the instances of
+    // a real batch do: with one shared histogram the trial's credits would
+    // contend on the same bins, which favours LDS staging over direct
+    // atomics.  Up to 64 GiB of trial histograms; beyond that they share
+    // the scratch result's.
+    double* trial_hist = nullptr;
+    const size_t hist_bytes = (size_t)nb * sizeof(double);
+    if (2 * hist_bytes * (size_t)instances <= (size_t)64 << 30) {
+        e = hipMalloc(&trial_hist, 2 * hist_bytes * (size_t)instances);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trial_hist = nullptr;
+        }
+    }
     float best = -1.0f;
     LaunchShape best_s{};
     const int ropts[4] = {1, 4, 16, 64}, wopts[3] = {1, 4, 16};
     // histogram staging (narrow kernels): off, flushed at the step's end, or
     // also every 64 rounds
     const int sopts[3] = {-1, 0, 64};
-    const int nst = narrow_kernel(nsc, mc) ? 3 : 1;
     for (int a = 0; a < 4 && !rc; ++a)
         for (int b = 0; b < 3 && !rc; ++b)
-        for (int c = 0; c < nst && !rc; ++c) {
+        for (int c = 0; c < ((narrow_kernel(nsc, mc) && ropts[a] <= 4 && wopts[b] <= 4) ? 3 : 1) &&
+                        !rc;
+             ++c) {
             LaunchShape s{ropts[a], wopts[b], nsc, mc};
             s.stage_flush = sopts[c];
             const int64_t cap = (int64_t)s.rpl * s.waves * 64;
             if (cap < R || cap > 16 * (int64_t)std::max(R, 64) || !shape_supported(s)) continue;
-            // all trial instances write the same (scratch) outputs: only the
-            // time of the instance kernel is kept
+            // the trial instances share the scratch result's other outputs:
+            // only the time of the launch is kept
             std::vector<DevInst> insts((size_t)instances);
             for (int i = 0; i < instances; ++i) {
                 parrep_problem q = *prob;
@@ -256,6 +271,10 @@ int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem
                 q.max_events = trial_events;
                 fill_inst(insts[i], net, &q, nb);
                 attach_result(insts[i], scratch);
+                if (trial_hist) {
+                    insts[i].hist = trial_hist + (size_t)(2 * i) * (size_t)nb;
+                    insts[i].hist_w = trial_hist + (size_t)(2 * i + 1) * (size_t)nb;
+                }
                 insts[i].cycle_log = nullptr;
                 insts[i].cycle_log_cap = 0;
             }
@@ -277,6 +296,7 @@ int parrep_autotune(parrep_ctx* ctx, const parrep_net* net, const parrep_problem
     (void)hipEventDestroy(eb);
     (void)hipEventDestroy(ea);
     (void)hipStreamDestroy(st);
+    if (trial_hist) (void)hipFree(trial_hist);
     if (rc) return rc;
     if (best < 0.0f) return fail(PARREP_EUNSUPPORTED, "no compiled launch shape holds R replicas");
     {

@@ -1132,7 +1132,8 @@ __device__ __forceinline__ void block_min_sum(Shared<E, WAVES>& sh, int& par, in
     __syncthreads();
     omin = INT_MAX;
     uint64_t a = 0, b = 0, c = 0;
-#pragma unroll
+    // partly unrolled: with 16 waves a full unroll keeps every partial live
+#pragma unroll 4
     for (int w = 0; w < WAVES; ++w) {
         omin = min(omin, sh.wmin[p][w]);
         a += sh.wsum[p][w][0];
@@ -1336,19 +1337,24 @@ __device__ __forceinline__ void decorrelate(const HotNet<M>& h, const DevInst* _
 // ---------------------------------------------------------------------------
 // The instance kernel: one workgroup runs Alg. 1 for one instance.
 // ---------------------------------------------------------------------------
-// Occupancy target per shape: with 4 replicas per lane the allocator is
-// asked to fit 5 waves per SIMD (at most 96 VGPRs; the few spills fall
-// outside the per-event path), which is also what the LDS of a 4-wave
-// workgroup allows (5 x 28.6 KB); other shapes fit their natural size.
-template <int RPL>
-constexpr int kMinWavesPerEU = RPL == 4 ? 5 : 1;
+// Occupancy target per shape: with 4 replicas per lane and workgroups of at
+// most 4 waves the allocator is asked to fit 5 waves per SIMD (at most 96
+// VGPRs; the few spills fall outside the per-event path), which is also what
+// the LDS of a 4-wave workgroup allows (5 x 28.6 KB).  Other shapes fit their
+// natural size: a 16-wave workgroup puts 4 waves on each SIMD, so a 5-wave
+// target would only cap its registers (and spill) for no occupancy.
+template <int RPL, int WAVES>
+constexpr int kMinWavesPerEU = (RPL == 4 && WAVES <= 4) ? 5 : 1;
 
 // SPEC >= 0: a compiled specialisation.  Narrow kernels: one species map
 // (bit j: the species that reaction j's table is read at), with rows at a
 // fixed stride.  General kernels: one network descriptor (desc_pack).
-template <int NS, int M, int RPL, int WAVES, long long SPEC = -1>
+// STAGE: the histogram-staging build of the parallel step (narrow kernels,
+// at most 4 replicas per lane and 4 waves); the other builds carry none of
+// its code, whose calls would add register pressure and spills.
+template <int NS, int M, int RPL, int WAVES, long long SPEC = -1, bool STAGE = false>
 __global__ void __launch_bounds__(64 * WAVES)
-__attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL>, 8)))
+__attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL, WAVES>, 8)))
 k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
            int64_t hook_max_rounds, int tab_lds) {
     constexpr int B = 64 * WAVES;
@@ -1723,7 +1729,8 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
         // flushed with one atomic per visited bin.  Decided here, so that
         // nothing of it is live during the other steps.
         const int stage_flush = I->stage_flush;
-        const bool stage = narrow_kernel(NS, M) && accum && stage_flush >= 0;
+        constexpr bool kStageable = STAGE && narrow_kernel(NS, M) && RPL <= 4 && WAVES <= 4;
+        const bool stage = kStageable && accum && stage_flush >= 0;
         double* tile = ltab + tab_lds;
         TileWin tw{0, 0, 0, 0};
         bool tile_win = false;  // the tile holds time after the burn-in time

@@ -25,6 +25,24 @@ hipError_t launch_instance(const DevInst* d, int n, int mode, uint32_t hc, int64
     // that stage it
     const size_t lead = (xbuf_lds_bytes(RPL, WAVES, NS) / 4 + 1) / 2 * 8;
     const size_t lds = lead + (size_t)tab_lds * 8 + (stage ? (size_t)kTileDoubles * 8 : 0);
+    // the staging builds: narrow kernels with at most 4 replicas per lane and
+    // 4 waves (the host stages no other shape)
+    if (stage) {
+        if constexpr (narrow_kernel(NS, M) && RPL <= 4 && WAVES <= 4) {
+            if constexpr (NS == 2 && M == 4) {
+                if (spec == kMapCross) {
+                    hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES, kMapCross, true>), dim3(n),
+                                       dim3(64 * WAVES), lds, st, d, mode, hc, hmr, tab_lds);
+                    return hipGetLastError();
+                }
+            }
+            if (spec >= 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES, -1, true>), dim3(n), dim3(64 * WAVES),
+                               lds, st, d, mode, hc, hmr, tab_lds);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if constexpr (NS == 2 && M == 4) {
         if (spec == kMapCross) {
             hipLaunchKernelGGL((k_instance<NS, M, RPL, WAVES, kMapCross>), dim3(n),
