@@ -240,6 +240,18 @@ def forms(B, W, ctx, args, laws=None):
     bh = [o.to_host() for o in plan.outputs]
     plan.close()
     log("forms: batched %d instances in %.2f s" % (len(probs), t_batch))
+    # the same plan in the persistent form (resident workgroups taking each
+    # group's instances from a counter), timed the same way
+    pplan = B.Plan(probs, ctx=ctx, persistent=1)
+    pplan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pplan.launch()
+    torch.cuda.synchronize()
+    t_pers = time.perf_counter() - t0
+    pers_h = [o.to_host() for o in pplan.outputs]
+    pplan.close()
+    log("forms: persistent batched %d instances in %.2f s" % (len(probs), t_pers))
 
     def plain_solves(ps):
         outs = []
@@ -339,6 +351,8 @@ def forms(B, W, ctx, args, laws=None):
                     "Omega~U{25..150} T=%g, R~logU[256,16384], %d-%d runs per request, "
                     "2%% RSE target)" % (Tt, Tt, runs_min, runs_max),
         "batched_solves_per_s": batched,
+        "batched_persistent_solves_per_s": len(probs) / t_pers,
+        "batched_persistent_equals_batched": all(same(a, b) for a, b in zip(pers_h, bh)),
         "plain_solves_per_s": plain,
         "batched_over_plain": batched / plain,
         "plain_sample": "all %d instances solved one at a time" % len(probs),

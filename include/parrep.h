@@ -217,6 +217,11 @@ typedef struct {
                                    the shape as replicas_per_lane and waves do          */
     int32_t flush_period;       /* staged: also flush every this many rounds (0 = only
                                    at the step's end and at the burn-in time)          */
+    int32_t persistent;         /* 0 = one workgroup per instance (the default); 1 = the
+                                   persistent form: as many workgroups as the device
+                                   holds at once, each taking the group's instances
+                                   (longest first) from a counter until all are run;
+                                   not with staging or spread instances               */
 } parrep_launch;
 
 /* Create a context on a HIP device: it owns the scratch arena and the

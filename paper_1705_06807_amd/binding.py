@@ -68,7 +68,7 @@ class Launch(C.Structure):
                 ("event_before", C.c_void_p), ("event_after", C.c_void_p),
                 ("workgroups", C.c_int32), ("chunk_rounds", C.c_int32 * 2),
                 ("barrier_wait_us", C.c_int32), ("histogram_staging", C.c_int32),
-                ("flush_period", C.c_int32)]
+                ("flush_period", C.c_int32), ("persistent", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -327,7 +327,7 @@ def parrep_solve_batch(problems: Sequence[W.Problem], ctx: Optional[Context] = N
                        cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None,
                        events=None, workgroups: int = 0, chunk_rounds=(0, 0),
                        barrier_wait_us: int = 0, histogram_staging: int = 0,
-                       flush_period: int = 0) -> List[Outputs]:
+                       flush_period: int = 0, persistent: int = 0) -> List[Outputs]:
     """Many independent solves in one launch; returns per-instance device outputs.
     workgroups, chunk_rounds, barrier_wait_us: see parrep_launch (spreading a
     single instance over workgroups)."""
@@ -338,7 +338,8 @@ def parrep_solve_batch(problems: Sequence[W.Problem], ctx: Optional[Context] = N
     ps = (Problem * n)(*[problem_struct(p) for p in problems])
     rs = (Result * n)(*[o.struct() for o in outs])
     la = Launch(replicas_per_lane, waves, None, None, workgroups,
-                (C.c_int32 * 2)(*chunk_rounds), barrier_wait_us, histogram_staging, flush_period)
+                (C.c_int32 * 2)(*chunk_rounds), barrier_wait_us, histogram_staging, flush_period,
+                persistent)
     if events is not None:  # (before, after) torch.cuda.Event pair, already created
         la.event_before, la.event_after = events[0].cuda_event, events[1].cuda_event
     _check(lib().parrep_solve_batch(ctx.h, n, nets, ps, rs, C.byref(la), _stream_ptr(stream)))
@@ -446,7 +447,7 @@ class Plan:
     def __init__(self, problems: Sequence[W.Problem], ctx: Optional[Context] = None,
                  cycle_log_cap: int = 0, outputs: Optional[List[Outputs]] = None,
                  replicas_per_lane: int = 0, waves: int = 0, histogram_staging: int = 0,
-                 flush_period: int = 0):
+                 flush_period: int = 0, persistent: int = 0):
         self.ctx = ctx or context()
         n = len(problems)
         self.problems = list(problems)
@@ -457,6 +458,7 @@ class Plan:
         rs = (Result * n)(*[o.struct() for o in self.outputs])
         la = Launch(replicas_per_lane, waves, None, None)
         la.histogram_staging, la.flush_period = histogram_staging, flush_period
+        la.persistent = persistent
         h = C.c_void_p()
         _check(lib().parrep_plan_create(self.ctx.h, n, nets, ps, rs, C.byref(la), C.byref(h)))
         self.h = h

@@ -299,7 +299,7 @@ LaunchShape pick_shape(parrep_ctx* ctx, int R, int ns, int m, bool sparse) {
 }
 
 std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
-                               std::vector<int>* order, const LaunchShape* forced) {
+                               std::vector<int>* order, const LaunchShape* forced, bool persist) {
     const int n = (int)insts.size();
     std::vector<LaunchShape> sh(n);
     for (int i = 0; i < n; ++i) {
@@ -353,6 +353,8 @@ std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
             if (table_lds_doubles(t, need) < need) spec = -1;
         }
         g.shape.spec = spec;
+        // the persistent form, when asked for (not with staging)
+        g.shape.persist = persist && g.shape.stage_flush < 0 ? 1 : 0;
         int need = 0;
         for (int i = g.first; i < g.first + g.count; ++i) {
             need = std::max(need, table_lds_need(insts[i], g.shape));
@@ -444,6 +446,7 @@ int apply_wide(parrep_ctx* ctx, std::vector<DevInst>& insts, std::vector<Group>&
     g.shape.waves = 4;
     g.shape.wide = G;
     g.shape.spec = -1;
+    g.shape.persist = 0;
     g.tab_lds = table_lds_doubles(g.shape, table_lds_need(d, g.shape));
     d.wide_waves = 4 * G;
     d.wide_rpl = rpl;
@@ -459,7 +462,8 @@ int run_batch(parrep_ctx* ctx, std::vector<DevInst>& insts, int mode, uint32_t h
               const LaunchShape* forced, const WideReq* wide) {
     int rc = set_device(ctx);
     if (rc) return rc;
-    std::vector<Group> groups = group_batch(ctx, insts, nullptr, forced);
+    std::vector<Group> groups =
+        group_batch(ctx, insts, nullptr, forced, mode == kModeSolve && wide && wide->persist);
     if (mode == kModeSolve) {
         rc = apply_wide(ctx, insts, groups, wide ? *wide : WideReq{});
         if (rc) return rc;
@@ -701,6 +705,9 @@ int parrep_solve_batch(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
         wide.s2 = launch->chunk_rounds[0];
         wide.s3 = launch->chunk_rounds[1];
         wide.wait_us = launch->barrier_wait_us;
+        if (launch->persistent < 0 || launch->persistent > 1)
+            return fail(PARREP_EINVAL, "persistent must be 0 or 1");
+        wide.persist = launch->persistent;
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
     return run_batch(ctx, insts, kModeSolve, 0, -1, (hipStream_t)stream, ev_b, ev_a,

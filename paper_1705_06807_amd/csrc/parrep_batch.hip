@@ -99,7 +99,12 @@ int parrep_plan_create(parrep_ctx* ctx, int32_t count, const parrep_net* const* 
         return rc;
     }
     std::vector<int> order;
-    p->groups = group_batch(ctx, insts, &order, force ? &forced : nullptr);
+    if (launch && (launch->persistent < 0 || launch->persistent > 1)) {
+        delete p;
+        return fail(PARREP_EINVAL, "persistent must be 0 or 1");
+    }
+    p->groups = group_batch(ctx, insts, &order, force ? &forced : nullptr,
+                            launch && launch->persistent == 1);
     p->slot.resize(count);
     for (int k = 0; k < count; ++k) p->slot[order[k]] = k;
     hipError_t e = hipMalloc(&p->base, arena_bytes(insts, false));

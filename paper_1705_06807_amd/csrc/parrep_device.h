@@ -1353,10 +1353,9 @@ constexpr int kMinWavesPerEU = (RPL == 4 && WAVES <= 4) ? 5 : 1;
 // at most 4 replicas per lane and 4 waves); the other builds carry none of
 // its code, whose calls would add register pressure and spills.
 template <int NS, int M, int RPL, int WAVES, long long SPEC = -1, bool STAGE = false>
-__global__ void __launch_bounds__(64 * WAVES)
-__attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL, WAVES>, 8)))
-k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
-           int64_t hook_max_rounds, int tab_lds) {
+__device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int mode,
+                                              uint32_t hook_cycle, int64_t hook_max_rounds,
+                                              int tab_lds) {
     constexpr int B = 64 * WAVES;
     // With one replica per lane a dephasing or parallel round is one
     // dependent chain per wave, so little hides its latency.  The uniforms
@@ -1376,7 +1375,6 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
     __shared__ Shared<E, WAVES> sh;
     extern __shared__ int32_t dyn_lds[];
 
-    const DevInst* __restrict__ I = insts + blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
@@ -1980,6 +1978,37 @@ k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
             I->phase_clock[2] = (int64_t)rs.clk[2];
             I->phase_clock[3] = (int64_t)(wall_clock64() - rs.clk[3]);
         }
+    }
+}
+
+// One workgroup per instance: workgroup b runs instance b.
+template <int NS, int M, int RPL, int WAVES, long long SPEC = -1, bool STAGE = false>
+__global__ void __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL, WAVES>, 8)))
+k_instance(const DevInst* __restrict__ insts, int mode, uint32_t hook_cycle,
+           int64_t hook_max_rounds, int tab_lds) {
+    instance_body<NS, M, RPL, WAVES, SPEC, STAGE>(insts + blockIdx.x, mode, hook_cycle,
+                                                  hook_max_rounds, tab_lds);
+}
+
+// Persistent form of a solve launch: a grid of at most as many workgroups as
+// the device holds at once, each taking the next instance from the group's
+// counter (next, zeroed before the launch) until all n are taken.  Instances
+// run in index order of taking, which the host sorts longest first; each
+// runs exactly as in k_instance.
+template <int NS, int M, int RPL, int WAVES, long long SPEC = -1>
+__global__ void __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<RPL, WAVES>, 8)))
+k_persist(const DevInst* __restrict__ insts, int n, int* next, int tab_lds) {
+    __shared__ int take;
+    for (;;) {
+        if (threadIdx.x == 0) take = atomicAdd(next, 1);
+        __syncthreads();
+        const int i = take;
+        __syncthreads();  // every thread has read take before it changes
+        if (i >= n) break;
+        instance_body<NS, M, RPL, WAVES, SPEC>(insts + i, kModeSolve, 0, -1, tab_lds);
+        __syncthreads();  // the instance's last LDS reads before the next one's writes
     }
 }
 

@@ -77,7 +77,8 @@ struct Group {
     int first, count, tab_lds;
 };
 std::vector<Group> group_batch(parrep_ctx* ctx, std::vector<DevInst>& insts,
-                               std::vector<int>* order, const LaunchShape* forced);
+                               std::vector<int>* order, const LaunchShape* forced,
+                               bool persist = false);
 
 // Enqueue setup, zero, the group launches (side by side on the context's
 // auxiliary streams, joined back into st), finalize.  d: device copy of the
@@ -97,6 +98,7 @@ struct WideReq {
     int rpl = 0;         // replicas per lane, 1 or 4 (0: 1)
     int s2 = 0, s3 = 0;  // chunk lengths in rounds (0: defaults)
     int wait_us = 0;     // longest wait at a grid barrier (0: 2 s)
+    int persist = 0;     // 1: the persistent form of the groups' solve launches
 };
 // Rewrites the only group of a one-instance solve to the wide kernel when w
 // asks for it or R is large, and sets the instance's wide fields (before

@@ -198,6 +198,9 @@ struct LaunchShape {
     // compiled specialisation every instance of the group fits (-1: none):
     // a species map (narrow kernels) or a network descriptor (general kernels)
     long long spec = -1;
+    // 1: the persistent form of a solve launch (k_persist: resident
+    // workgroups take the group's instances from a counter)
+    int persist = 0;
 };
 
 // Launchers (parrep_kernels.hip).

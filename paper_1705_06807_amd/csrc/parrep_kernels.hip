@@ -427,7 +427,7 @@ LaunchShape choose_shape(int R, int ns, int m) {
 
 #define PARREP_DECL(NSv, Wv)                                                                  \
     hipError_t launch_instance_ns##NSv##_w##Wv(const DevInst*, int, int, int, int, uint32_t,     \
-                                               int64_t, int, int, long long, hipStream_t);
+                                               int64_t, int, int, long long, int, hipStream_t);
 PARREP_DECL(1, 1) PARREP_DECL(1, 4) PARREP_DECL(1, 16)
 PARREP_DECL(2, 1) PARREP_DECL(2, 4) PARREP_DECL(2, 16)
 PARREP_DECL(4, 1) PARREP_DECL(4, 4) PARREP_DECL(4, 16)
@@ -441,7 +441,7 @@ hipError_t launch_solve(const DevInst* d_inst, int n_inst, LaunchShape s, int mo
     if (s.ns == NSv && s.waves == Wv)                                                         \
         return launch_instance_ns##NSv##_w##Wv(d_inst, n_inst, s.m, s.rpl, mode, hook_cycle,  \
                                                hook_max_rounds, tab_lds, s.stage_flush >= 0,   \
-                                               s.spec, stream);
+                                               s.spec, s.persist, stream);
     PARREP_GO(1, 1) PARREP_GO(1, 4) PARREP_GO(1, 16)
     PARREP_GO(2, 1) PARREP_GO(2, 4) PARREP_GO(2, 16)
     PARREP_GO(4, 1) PARREP_GO(4, 4) PARREP_GO(4, 16)

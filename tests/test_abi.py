@@ -52,7 +52,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(B.Factor) == 6 * 4 + 8
     assert ctypes.sizeof(B.Reaction) == 8 + 8 + 16 + 2 * 32
     assert ctypes.sizeof(B.Result) == 6 * 8 + 8 + 8
-    assert ctypes.sizeof(B.Launch) == 48
+    assert ctypes.sizeof(B.Launch) == 56
+    assert B.Launch.persistent.offset == 48
     assert ctypes.sizeof(B.Request) == 8 + 4 + 4 + 8
     assert ctypes.sizeof(B.RequestInfo) == 4 + 4 + 8 + 8 + 8 + 4 * 8
     assert B.Problem.max_events.offset + 8 == ctypes.sizeof(B.Problem)

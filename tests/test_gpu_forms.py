@@ -197,6 +197,50 @@ def test_plan_with_general_kernels_and_large_r(B, oracle):
     plan.close()
 
 
+def test_persistent_batch_equals_one_workgroup_per_instance(B, oracle):
+    """The persistent form (resident workgroups taking the instances of their
+    group from a counter) gives every instance the result it gets with a
+    workgroup of its own: narrow and general kernels, several shape groups,
+    as a batch and as a plan replayed twice; one instance against the
+    oracle."""
+    import torch
+    probs = _general_mix()[:3] + _mixed(seed=3, n=3)
+    _flush("persistent batch over %d instances, R in %s" % (len(probs), sorted(p.R for p in probs)))
+    eager = _host(B.parrep_solve_batch(probs, cycle_log_cap=0))
+    pers = _host(B.parrep_solve_batch(probs, cycle_log_cap=0, persistent=1))
+    for i, (g, e) in enumerate(zip(pers, eager)):
+        assert_gpu_same(g, e, what="persistent batch instance %d" % i)
+    plan = B.Plan(probs, persistent=1)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        got = [o.to_host() for o in plan.outputs]
+        for i, (g, e) in enumerate(zip(got, eager)):
+            assert_gpu_same(g, e, what="persistent plan replay %d instance %d" % (rep, i))
+    plan.close()
+    o = oracle.run(probs[0], cycle_log_cap=0)
+    pers[0].cycle_log = None
+    o.cycle_log = None
+    assert_same(o, pers[0], what="persistent vs oracle")
+
+
+def test_persistent_batch_takes_more_instances_than_the_device_holds(B):
+    """1500 instances in 16-wave workgroups, more than the device holds at
+    once: each resident workgroup runs several instances in turn."""
+    probs = [W.c1_schlogl(seed=21, instance_id=i, R=32, T=2.0) for i in range(1500)]
+    _flush("persistent batch of %d instances, shape (1,16)" % len(probs))
+    eager = _host(B.parrep_solve_batch(probs, replicas_per_lane=1, waves=16))
+    pers = _host(B.parrep_solve_batch(probs, replicas_per_lane=1, waves=16, persistent=1))
+    for i, (g, e) in enumerate(zip(pers, eager)):
+        assert_gpu_same(g, e, what="instance %d" % i)
+    assert all(h.T_s == 2.0 for h in pers)
+
+
+def test_persistent_rejects_bad_value(B):
+    with pytest.raises(B.ParrepError, match="persistent"):
+        B.parrep_solve_batch([W.c1_schlogl(seed=0, instance_id=0, T=1.0)], persistent=2)
+
+
 def test_server_with_general_kernels(B):
     reqs = [(p, 2) for p in _general_mix()[:4]]
     srv = B.Server(n_streams=4)
