@@ -48,7 +48,7 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "719e3f8e3aadd9a68e507dc1054ba8adf620dca123de7d71b29cb455594d8cf8",
+           "sources_sha256": "08ff00ba8bd68ca428a4605ff3f705f5756aee08f8f2267231700320d046e96b",
            "fetch_kib": 1931122.8125, "write_kib": 5687400387.5625,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 

@@ -13,6 +13,13 @@
 // evaluated in Estrin form.  The
 // two sub-intervals next to z = 1 use invc = 1, log c = 0, so u -> 1 keeps
 // full relative accuracy and u = 1 gives -0.0 as the C library log does.
+//
+// The method is P. T. P. Tang's table-driven logarithm ("Table-driven
+// implementation of the logarithm function in IEEE floating-point
+// arithmetic", ACM TOMS 16(4), 1990), in the form with the reduction
+// interval [0.6875, 1.375) and a 128-entry 1/c, log c table that Arm's
+// Optimized Routines use for log.  The table here is computed at run time
+// from long double logl, and the polynomial is the plain Taylor series.
 #pragma once
 #include <cmath>
 #include <cstdint>
