@@ -108,17 +108,14 @@ __device__ __forceinline__ double u_open(const Blk& b) {
 }
 
 __device__ __forceinline__ double u_sel(const Blk& b) {
-    // (w >> 11) 2^-53 as hi 2^-21 + lo 2^-53 with hi = w3 >> 11 and lo the next
-    // 32 bits: both terms and their sum are exact
-    const uint32_t hi = b.w3 >> 11;
-    const uint32_t lo = (b.w3 << 21) | (b.w2 >> 11);
-    return fma((double)hi, 0x1.0p-21, (double)lo * 0x1.0p-53);
+    // (w >> 11) 2^-53 for w = w3:w2, as w3 2^-32 + (w2 >> 11) 2^-53: both
+    // terms and their sum (a 53-bit integer times 2^-53) are exact
+    return fma((double)b.w3, 0x1.0p-32, (double)(b.w2 >> 11) * 0x1.0p-53);
 }
 
 // -log(u_open(b)); lt: the reduction table in LDS.
 __device__ __forceinline__ double neglog_u_open(const Blk& b, const double* __restrict__ lt) {
-    const uint64_t w = ((uint64_t)b.w1 << 32) | b.w0;
-    return neglog_u53((w >> 11) + 1, lt);
+    return neglog_words53(b.w1, b.w0, lt);
 }
 
 // Values known to be equal in all lanes, moved to scalar registers.

@@ -37,9 +37,8 @@ constexpr int kLogTabLen = 3 * kLogTabN;  // invc | logc_hi | logc_lo
 constexpr double kLn2Hi = 0x1.62e42fefa3a00p-1;
 constexpr double kLn2Lo = -0x1.0ca86c3898d00p-49;
 
-// m in [1, 2^53]; returns -log(m * 2^-53).
-PARREP_HD inline double neglog_u53(uint64_t m, const double* __restrict__ lt) {
-    const double d = std::fma((double)(uint32_t)(m >> 32), 0x1.0p32, (double)(uint32_t)m);  // exact
+// d = m as a double (exact), m in [1, 2^53]; returns -log(m * 2^-53).
+PARREP_HD inline double neglog_d53(double d, const double* __restrict__ lt) {
     const uint64_t db = __builtin_bit_cast(uint64_t, d);
     const uint32_t dh = (uint32_t)(db >> 32);
     const uint32_t t = dh - 0x3FE60000u;  // high word of bits(d) - bits(0.6875): no borrow
@@ -60,6 +59,18 @@ PARREP_HD inline double neglog_u53(uint64_t m, const double* __restrict__ lt) {
     const double q = std::fma(r2, std::fma(r2, qc, qb), qa);
     const double p = std::fma(r2, q, r);
     return -(a + (s1 + p));
+}
+
+// m in [1, 2^53]; returns -log(m * 2^-53).
+PARREP_HD inline double neglog_u53(uint64_t m, const double* __restrict__ lt) {
+    return neglog_d53(std::fma((double)(uint32_t)(m >> 32), 0x1.0p32, (double)(uint32_t)m), lt);
+}
+
+// The same for m = (hi:lo >> 11) + 1 of two 32-bit words: m = hi 2^21 +
+// ((lo >> 11) + 1), both terms exact doubles and their sum (at most 2^53)
+// exact, so no 64-bit integer is formed.
+PARREP_HD inline double neglog_words53(uint32_t hi, uint32_t lo, const double* __restrict__ lt) {
+    return neglog_d53(std::fma((double)hi, 0x1.0p21, (double)((lo >> 11) + 1u)), lt);
 }
 
 // Host: fill lt[kLogTabLen].  log(1/invc) in long double (64-bit mantissa:
