@@ -36,7 +36,7 @@ METRIC = "SSA events/s on 1 GPU (% VALU peak); batched/served ParRep solves/s + 
 VALU_SLOTS_PER_EVENT = 98
 # FP64 VALU instructions per event in the built kernel (rocprofv3 counters
 # SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 over events, toggle workload).
-FP64_OPS_PER_EVENT_ISA = 26.41
+FP64_OPS_PER_EVENT_ISA = 25.41
 # MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz, a wave64 VALU op takes 4 cycles
 # -> 256*4*16*2.4e9 = 3.93e13 lane-op slots per second.
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
@@ -48,8 +48,8 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "08ff00ba8bd68ca428a4605ff3f705f5756aee08f8f2267231700320d046e96b",
-           "fetch_kib": 1931122.8125, "write_kib": 5687400387.5625,
+           "sources_sha256": "60763f1e90bf0bb742a169593dacdfbdc00bf039f0a2b20aaa4dd19b39a85ba2",
+           "fetch_kib": 1932689.875, "write_kib": 5687400751.875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
 
