@@ -1459,6 +1459,7 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
         }
         const uint32_t cycle = ufl((uint32_t)rs.cycle);
         const int W = ufl(rs.W);
+        const bool inW1 = W != 0;  // W is set 0 or set 1
         int xt[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) xt[i] = ufl(rs.xt[i]);
@@ -1476,7 +1477,8 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
                 tr[k] = 0.0;
             }
             const bool steps = I->dephase_mode == PARREP_STEPS;
-            const int64_t n_p = (int64_t)I->dephase;
+            // uniform (the conversion from double runs on the vector unit)
+            const int64_t n_p = (int64_t)ufl64((uint64_t)(int64_t)I->dephase);
             const double t_p = I->dephase;
             const int64_t left2 = (max_ev - rs.ev_total) / R;
             // round 0's uniforms (one replica per lane: see kAhead)
@@ -1489,12 +1491,14 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
             int64_t fv = 0;
             // One dephasing round n of this thread's replicas: the slots whose
             // replica left W; nd is set when one is still short of t_p.
-            auto dephase_round = [&](int64_t n, bool& nd) -> SlotMask {
+            // full (a std::integral_constant) is true when every slot of every
+            // thread holds a replica (R = RPL * B): no per-slot lane masks.
+            auto dephase_round = [&](int64_t n, bool& nd, auto full) -> SlotMask {
                 SlotMask exitbits = 0;
-#pragma unroll kUK
+#pragma unroll (RPL <= 16 ? RPL : 1)
                 for (int k = 0; k < RPL; ++k) {
                     const int r = k * B + tid;
-                    if (r < R) {
+                    if (decltype(full)::value || r < R) {
                         Uni u;
                         if constexpr (kAhead) {
                             u = ahead;
@@ -1513,7 +1517,10 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
                                                          dxp);
                         apply_dx<NS>(Y[k], dxp);
                         tr[k] = tr[k] + tau;
-                        exitbits |= (SlotMask)(region_hot<NS, M>(hn, Y[k]) != W ? 1 : 0) << k;
+                        // left W: the region (0 or 1) differs from W, as an
+                        // exclusive or of two conditions
+                        const bool out = (region_hot<NS, M>(hn, Y[k]) != 0) != inW1;
+                        exitbits |= (SlotMask)(out ? 1 : 0) << k;
                         nd = nd | !(tr[k] >= t_p);
                     }
                 }
@@ -1584,8 +1591,13 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
             // rounds, is known in advance in STEPS mode.)
             const bool chunked = kChunkS2 && steps;
             int64_t chunk = 0;
+            // round2 never passes budget_rounds or (STEPS mode) n_p: it grows by
+            // one per round, and a chunk's length is capped by both.  So the
+            // loop's tests are equalities of uniform 64-bit values, which the
+            // scalar unit takes (it has no ordered 64-bit compare).
+            auto s2_rounds = [&](auto full) {
             while (!done) {
-                if (round2 >= budget_rounds) {
+                if (round2 == budget_rounds) {
                     budget = true;
                     break;
                 }
@@ -1604,7 +1616,7 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
                     int64_t ew = INT64_MAX;
                     bool nd = false;
                     for (int64_t n = c0; n < c0 + L; ++n) {
-                        exitbits = dephase_round(n, nd);
+                        exitbits = dephase_round(n, nd, full);
                         if (__ballot(exitbits != 0) != 0ull) {
                             ew = n;
                             break;
@@ -1627,17 +1639,17 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
 #pragma unroll
                                 for (int i = 0; i < NS; ++i) Y[k][i] = Y0[k][i];
                             ahead = ahead0;
-                            for (int64_t n = c0; n <= ef; ++n) exitbits = dephase_round(n, nd);
+                            for (int64_t n = c0; n <= ef; ++n) exitbits = dephase_round(n, nd, full);
                         }
                         fv_restart(ef, exitbits);
                         round2 = ef + 1;
                     }
-                    done = round2 >= n_p;
+                    done = round2 == n_p;
                     continue;
                 }
                 const int p = (int)(round2 & 1);
                 bool nd = false;
-                const SlotMask exitbits = dephase_round(round2, nd);
+                const SlotMask exitbits = dephase_round(round2, nd, full);
                 // One barrier per round: each wave posts whether one of its
                 // replicas left W and whether one is still short of t_p.  The
                 // flags alternate between two slots, so the posts of round
@@ -1652,7 +1664,16 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
                 fl = ufl(fl);
                 if (fl & 2) fv_restart(round2, exitbits);
                 ++round2;
-                done = steps ? (round2 >= n_p) : ((fl & 1) == 0);
+                done = steps ? (round2 == n_p) : ((fl & 1) == 0);
+            }
+            };
+            if constexpr (RPL > 1) {
+                if (R >= RPL * B)
+                    s2_rounds(std::true_type{});
+                else
+                    s2_rounds(std::false_type{});
+            } else {
+                s2_rounds(std::false_type{});
             }
             __syncthreads();
             if (tid == 0) {

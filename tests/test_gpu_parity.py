@@ -221,6 +221,46 @@ def test_launch_shapes_agree(B, oracle, shape):
         assert_same(oracle.run(p, cycle_log_cap=4096), o.to_host(), what=str(shape))
 
 
+@pytest.mark.parametrize("shape,R", [((4, 1), 256), ((4, 1), 255), ((16, 1), 1024),
+                                     ((4, 4), 1024), ((4, 4), 1023)])
+@pytest.mark.parametrize("steps", [False, True])
+def test_full_slot_dephasing(B, oracle, shape, R, steps):
+    """Dephasing rounds in which every slot of every thread holds a replica
+    (R = replicas per lane x 64 x waves) run without per-slot lane masks;
+    one replica fewer takes the masked rounds.  Both against the oracle, with
+    the dephasing phase ended by time and by a round count."""
+    import torch
+    kw = dict(R=R, T=40.0)
+    if steps:
+        kw.update(dephase_mode=W.STEPS, dephase=12)
+    probs = [_toggle_small(i, **kw) for i in range(2)]
+    _flush("full-slot dephasing shape %s R=%d steps=%s" % (shape, R, steps))
+    outs = B.parrep_solve_batch(probs, replicas_per_lane=shape[0], waves=shape[1],
+                                cycle_log_cap=4096)
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        assert_same(oracle.run(p, cycle_log_cap=4096), o.to_host(),
+                    what="full-slot %s R=%d" % (shape, R))
+
+
+@pytest.mark.parametrize("shape,R", [((4, 1), 256), ((4, 4), 1024)])
+def test_full_slot_dephasing_budget(B, oracle, shape, R):
+    """An event budget that runs out inside the dephasing phase, in the
+    rounds without per-slot lane masks: the run stops there (end phase 9)
+    exactly as the oracle's does."""
+    import torch
+    probs = [_toggle_small(i, R=R, T=40.0, max_events=(R * 30 + 517, R * 58 + 3)[i])
+             for i in range(2)]
+    _flush("full-slot dephasing budget shape %s R=%d" % (shape, R))
+    outs = B.parrep_solve_batch(probs, replicas_per_lane=shape[0], waves=shape[1],
+                                cycle_log_cap=4096)
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        ref = oracle.run(p, cycle_log_cap=4096)
+        assert ref.counters["end_phase"] == 9
+        assert_same(ref, o.to_host(), what="full-slot budget %s R=%d" % (shape, R))
+
+
 @pytest.mark.parametrize("shape,R", [((1, 4), 230), ((1, 16), 700)])
 def test_chunked_dephasing_replays(B, oracle, shape, R):
     """STEPS-mode dephasing with one replica per lane over several waves runs
