@@ -1655,8 +1655,12 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
                 // flags alternate between two slots, so the posts of round
                 // n+1 never meet a slow wave's reads of round n.
                 const bool wave_exit = __ballot(exitbits != 0) != 0ull;
-                const bool wave_nd = __ballot(nd) != 0ull;
-                if (lane == 0) sh.flags[p][wid] = (wave_nd ? 1 : 0) | (wave_exit ? 2 : 0);
+                const bool wave_nd = __builtin_amdgcn_ballot_w64(nd) != 0ull;
+                // The flags are uniform, so every lane stores them (a relaxed
+                // atomic store of one value): no lane-0 mask in the round.
+                const int32_t f = (wave_nd ? 1 : 0) | (wave_exit ? 2 : 0);
+                __hip_atomic_store(&sh.flags[p][wid], f, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
                 __syncthreads();
                 int fl = 0;
 #pragma unroll
