@@ -48,8 +48,8 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "a28b1074a40c1b1647dc3b8e03a50ec0d1315e9ac04318bd688e31bda00c3a97",
-           "fetch_kib": 1921439.8125, "write_kib": 5687403053.3125,
+           "sources_sha256": "3dc4131f5851dc03e065f0e24d0a57f1b9969d69bfe26cb9f619b42a1ef9bdf1",
+           "fetch_kib": 1933383.625, "write_kib": 5687415772.0,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
 
