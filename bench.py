@@ -48,8 +48,8 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "3dc4131f5851dc03e065f0e24d0a57f1b9969d69bfe26cb9f619b42a1ef9bdf1",
-           "fetch_kib": 1933383.625, "write_kib": 5687415772.0,
+           "sources_sha256": "9335884a1ee7e75e6aca4a9009f7ea2db17c0bad496d085967e3a6616a37cb71",
+           "fetch_kib": 1933805.625, "write_kib": 5687417394.21875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 
 

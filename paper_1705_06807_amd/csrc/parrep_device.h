@@ -1492,7 +1492,8 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
             // One dephasing round n of this thread's replicas: the slots whose
             // replica left W; nd is set when one is still short of t_p.
             // full (a std::integral_constant) is true when every slot of every
-            // thread holds a replica (R = RPL * B): no per-slot lane masks.
+            // thread holds a replica (R = RPL * B): no per-slot lane masks
+            // (instantiated for RPL = 4, below).
             auto dephase_round = [&](int64_t n, bool& nd, auto full) -> SlotMask {
                 SlotMask exitbits = 0;
 #pragma unroll (RPL <= 16 ? RPL : 1)
@@ -1671,7 +1672,10 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
                 done = steps ? (round2 == n_p) : ((fl & 1) == 0);
             }
             };
-            if constexpr (RPL > 1) {
+            // Compiled for 4 replicas per lane only (the throughput shapes):
+            // a second copy of the fully unrolled 16-slot round would double
+            // the largest kernels' compile time for shapes that rarely run full.
+            if constexpr (RPL == 4) {
                 if (R >= RPL * B)
                     s2_rounds(std::true_type{});
                 else

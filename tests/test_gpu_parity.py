@@ -225,10 +225,11 @@ def test_launch_shapes_agree(B, oracle, shape):
                                      ((4, 4), 1024), ((4, 4), 1023)])
 @pytest.mark.parametrize("steps", [False, True])
 def test_full_slot_dephasing(B, oracle, shape, R, steps):
-    """Dephasing rounds in which every slot of every thread holds a replica
-    (R = replicas per lane x 64 x waves) run without per-slot lane masks;
-    one replica fewer takes the masked rounds.  Both against the oracle, with
-    the dephasing phase ended by time and by a round count."""
+    """With 4 replicas per lane, dephasing rounds in which every slot of
+    every thread holds a replica (R = 4 x 64 x waves) run without per-slot
+    lane masks; one replica fewer takes the masked rounds, as do the other
+    shapes (16 per lane).  All against the oracle, with the dephasing phase
+    ended by time and by a round count."""
     import torch
     kw = dict(R=R, T=40.0)
     if steps:
