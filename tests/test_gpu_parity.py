@@ -222,7 +222,8 @@ def test_launch_shapes_agree(B, oracle, shape):
 
 
 @pytest.mark.parametrize("shape,R", [((4, 1), 256), ((4, 1), 255), ((16, 1), 1024),
-                                     ((4, 4), 1024), ((4, 4), 1023)])
+                                     ((4, 4), 1024), ((4, 4), 1023), ((4, 16), 4096),
+                                     ((4, 16), 4095)])
 @pytest.mark.parametrize("steps", [False, True])
 def test_full_slot_dephasing(B, oracle, shape, R, steps):
     """With 4 replicas per lane, dephasing rounds in which every slot of
