@@ -295,7 +295,8 @@ def test_mixed_batch_equals_oracle(B, oracle):
 
 
 def test_dephase_hook(B, oracle):
-    for R, tp in ((64, 1.0), (1000, 0.5), (5000, 0.3)):
+    # R = 1024 takes shape (4, 4) with every slot full; 1000 the masked rounds
+    for R, tp in ((64, 1.0), (1000, 0.5), (1024, 0.5), (5000, 0.3)):
         p = W.c2_toggle(seed=3, omega=5.0, R=R).replace(dephase=tp)
         Yg, ng = B.parrep_dephase_only(p, (12, 3), cycle=7)
         Yo, no = oracle.dephase(p, (12, 3), cycle=7)
